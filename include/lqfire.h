@@ -1,0 +1,204 @@
+/*
+ * lqfire: lattice Landau-de Gennes force and FIRE relaxation on one MI355X.
+ *
+ * C ABI of liblqfire.so.  Method: Sussman & Beller, "Fast, scalable, and
+ * interactive software for Landau-de Gennes numerical modeling of nematic
+ * topological defects" (arXiv:1911.07045).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Lattice: nx * ny * nz sites, site s = x + nx*(y + ny*z), spacing 1.
+ *  - Per-site fields (q, v, F) are SoA: component c of site s at [c*N + s],
+ *    N = nx*ny*nz, five components (Qxx, Qxy, Qxz, Qyy, Qyz) with
+ *    Qzz = -Qxx - Qyy (sec. III.B).  Element type is double for LQ_F64 and
+ *    float for LQ_F32.  Field buffers are device memory on the device that was
+ *    current at lq_lattice_create, owned by the caller, 5*N elements each,
+ *    and must not overlap.
+ *  - All device work is enqueued on the stream given at lq_lattice_create.
+ *    Calls that return host values (lq_energy, lq_fire_step, lq_minimize,
+ *    lq_fire_init) synchronize that stream before returning; lq_compute_forces
+ *    and lq_set_uniaxial only enqueue.
+ *  - Every call returns LQ_OK (0) or a negative LQ_E* code; no exception or
+ *    abort crosses the ABI.  lq_last_error() gives a message.  Errors raised
+ *    by the device asynchronously surface as LQ_EHIP at the next call that
+ *    synchronizes.
+ *  - One lattice handle is used by one host thread at a time.  Handles are
+ *    independent of each other.
+ */
+#ifndef LQFIRE_H
+#define LQFIRE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define LQ_OK 0
+#define LQ_EINVAL (-1)        /* bad argument: sizes, pointers, NaN/negative parameters */
+#define LQ_EUNSUPPORTED (-2)  /* valid in the paper but not built: L4, L6, W_RP < 0 */
+#define LQ_ENOMEM (-3)        /* workspace too small, or a device allocation failed */
+#define LQ_EHIP (-4)          /* a HIP runtime call failed */
+#define LQ_ENONFINITE (-5)    /* a FIRE reduction produced NaN or Inf */
+#define LQ_ESTATE (-6)        /* call order: e.g. lq_fire_step before lq_fire_init */
+
+/* ---- precision of the state ---- */
+#define LQ_F64 0 /* q, v, F and all arithmetic in double */
+#define LQ_F32 1 /* q, v, F and per-site arithmetic in float; FIRE reductions,
+                    controller scalars and the energy sum in double */
+
+typedef struct lq_lattice lq_lattice;
+
+/* Lattice and constants (sec. III.B: everything in units of |A| and dx). */
+typedef struct {
+    int64_t n[3];        /* nx, ny, nz >= 1; >= 3 on a periodic axis */
+    int32_t periodic[3]; /* 1 = periodic axis, 0 = open (neighbours off the edge are absent) */
+    int32_t prec;        /* LQ_F64 or LQ_F32 */
+    double A, B, C;      /* bulk coefficients, Eq. (fphase); C > 0 */
+    double L1, L2, L3;   /* distortion coefficients, Eq. (fdistortionFull) */
+    double L4, L6;       /* must be 0 (LQ_EUNSUPPORTED otherwise) */
+} lq_params;
+
+/* Creates a lattice with every site bulk.  stream: a hipStream_t, or NULL for
+ * the null stream.  On success *out owns device tables of ~N bytes. */
+int lq_lattice_create(const lq_params* p, void* stream, lq_lattice** out);
+int lq_lattice_destroy(lq_lattice* lat);
+
+/* S0 of Eq. (S0def) for the lattice's A, B, C (NaN when it has no real value). */
+double lq_bulk_S0(const lq_lattice* lat);
+
+/* ---- geometry (sec. III.B site types; sec. II.D anchoring) ---- */
+#define LQ_OBJ_WALL 1           /* the lattice plane coordinate[axis] == plane */
+#define LQ_OBJ_SPHERE 2         /* sites with |x - center|^2 < radius^2, minimum image on periodic axes */
+#define LQ_OBJ_PATTERNED_WALL 3 /* a wall whose preferred director is the in-plane radial unit
+                                   vector away from the nearest centre of a square array */
+#define LQ_LAW_ND 0             /* W is the Nobili-Durand strength of W tr((Q - Q0)^2) */
+#define LQ_LAW_RP 1             /* W is a Rapini-Papoular strength; used as W / (9 S0^2) */
+#define LQ_DIR_NORMAL 0         /* preferred director = surface normal (homeotropic) */
+#define LQ_DIR_FIXED 1          /* preferred director = dir (oriented anchoring) */
+
+typedef struct {
+    int32_t kind;      /* LQ_OBJ_* */
+    int32_t law;       /* LQ_LAW_* */
+    int32_t dir_mode;  /* LQ_DIR_* (ignored by LQ_OBJ_PATTERNED_WALL) */
+    int32_t axis;      /* wall axis 0, 1, 2 */
+    int64_t plane;     /* wall plane index, 0 <= plane < n[axis] */
+    double W;          /* strength >= 0; W_RP < 0 (degenerate planar) is LQ_EUNSUPPORTED */
+    double center[3];  /* sphere centre (lattice units, any real value) */
+    double radius;     /* sphere radius > 0 */
+    double dir[3];     /* fixed preferred director (normalized by the library) */
+    double pitch[2];   /* patterned wall: centre spacing along the two in-plane axes (ascending order) */
+    double offset[2];  /* patterned wall: first centre */
+    int32_t count[2];  /* patterned wall: centres per in-plane axis */
+} lq_object;
+
+/* One extra anchoring term W tr((Q - Q0(n0))^2) at a simulated site: the
+ * paper's arbitrary per-site anchoring (its custom boundary files). */
+typedef struct {
+    int64_t site;
+    int32_t law; /* LQ_LAW_ND or LQ_LAW_RP */
+    int32_t pad;
+    double W;
+    double n0[3];
+} lq_site_anchor;
+
+/* Replaces the lattice geometry.  Every object marks its interior sites as
+ * inside an object (not simulated); object_sites marks extra ones.  A
+ * simulated site with a face neighbour inside object a carries one anchoring
+ * term of a (so a site touching two objects carries two); recs add more.
+ * Anchoring uses Q0 = 3/2 S0 (n0 n0 - I/3).  Host arrays; any may be NULL
+ * when its count is 0.  LQ_EINVAL on a bad object, a record at an object site
+ * or out of range, or S0 not real while anchoring is requested. */
+int lq_set_boundaries(lq_lattice* lat, const lq_object* objs, int32_t n_objs,
+                      const lq_site_anchor* recs, int64_t n_recs,
+                      const int64_t* object_sites, int64_t n_object_sites);
+
+/* Host-only form of the same rasterization (needs no GPU).  Writes the site
+ * type of every site to types (N bytes: 0 bulk, 1 boundary, 2 object; may be
+ * NULL) and, per anchored site in increasing site order, anch_site[i] and
+ * anch_data[7*i .. 7*i+6] = {sum W, sum W*Q0 (5 q-components),
+ * sum W*tr(Q0^2)}; at most cap entries are written (arrays may be NULL when
+ * cap is 0).  *n_anchored receives the full count. */
+int lq_rasterize(const lq_params* p, const lq_object* objs, int32_t n_objs,
+                 const lq_site_anchor* recs, int64_t n_recs, const int64_t* object_sites,
+                 int64_t n_object_sites, uint8_t* types, int64_t* n_anchored,
+                 int64_t* anch_site, double* anch_data, int64_t cap);
+
+/* Sets q = 3/2 S (n n - I/3) at simulated sites and 0 inside objects.
+ * directors: device, double, [3][N] unit vectors. */
+int lq_set_uniaxial(lq_lattice* lat, const double* directors, double S, void* q);
+
+/* ---- forces and energy (sec. III.B) ---- */
+
+/* F = -dE/dq of the discrete energy: bulk Eq. (fphase), distortion
+ * Eq. (fdistortionFull) with one-sided differences Eq. (onesidedderivatives)
+ * averaged over every allowed choice per axis, and anchoring.  F = 0 inside
+ * objects.  q and F: device, 5*N elements. */
+int lq_compute_forces(lq_lattice* lat, const void* q, void* F);
+
+typedef struct {
+    double bulk, elastic, anchoring, total;
+    int64_t n_sim; /* simulated sites */
+} lq_energy_terms;
+
+/* Discrete energy of q, summed in double in a fixed order. Synchronizes. */
+int lq_energy(lq_lattice* lat, const void* q, lq_energy_terms* out);
+
+/* ---- FIRE (Algorithm 1, after Bitzek et al. 2006) ---- */
+typedef struct {
+    double dt0, dt_max;  /* initial and largest time step */
+    double alpha0;       /* initial steering weight */
+    double f_inc, f_dec; /* time-step growth and shrink factors */
+    double f_alpha;      /* steering decay factor */
+    int64_t n_min;       /* steps with P > 0 before dt grows */
+    double force_tol;    /* converged when max |F_i| < force_tol */
+    int64_t max_steps;   /* stop after this many steps since lq_fire_init */
+} lq_fire_params;
+
+#define LQ_RUNNING 0
+#define LQ_CONVERGED 1
+#define LQ_MAX_STEPS 2
+#define LQ_NONFINITE 3
+
+typedef struct {
+    int64_t step;      /* steps taken since lq_fire_init (plus the resumed count) */
+    int64_t n_pos;     /* consecutive steps with P > 0 */
+    int64_t restarts;  /* steps that took the P <= 0 branch */
+    int32_t status;    /* LQ_RUNNING / LQ_CONVERGED / LQ_MAX_STEPS / LQ_NONFINITE */
+    int32_t pad;
+    double dt, alpha;  /* controller state for the next step */
+    double P, normF, normv, maxF; /* F.v, |F|, |v| (before steering) and max |F_i| of the last step */
+} lq_fire_report;
+
+/* Bytes of device workspace lq_fire_init needs: a second q, v, F for the
+ * ping-pong update, per-block partial sums and the device FIRE state. */
+int64_t lq_workspace_bytes(const lq_lattice* lat);
+
+/* Binds q, v, F and the workspace to the lattice and starts FIRE: F = F(q),
+ * dt = dt0, alpha = alpha0.  resume == NULL: v = 0 and counters at 0.
+ * resume != NULL: keeps the caller's v and takes step, n_pos, restarts, dt
+ * and alpha from *resume (a report saved earlier), so that a run can be
+ * continued bit for bit.  The buffers stay bound until the next
+ * lq_fire_init or lq_lattice_destroy. */
+int lq_fire_init(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F,
+                 void* workspace, int64_t workspace_bytes, const lq_fire_report* resume);
+
+/* Runs up to n_steps FIRE steps on the device with no host round trip
+ * between steps, stopping early on convergence, max_steps or a non-finite
+ * reduction.  On return the bound q, v, F hold the state after the last step
+ * (v after steering), and *out the controller.  LQ_ENONFINITE when the run
+ * hit a non-finite reduction. */
+int lq_fire_step(lq_lattice* lat, int64_t n_steps, lq_fire_report* out);
+
+/* lq_fire_init (fresh) + lq_fire_step until converged or max_steps. */
+int lq_minimize(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F,
+                void* workspace, int64_t workspace_bytes, lq_fire_report* out);
+
+/* Message for the last error on lat (or on the calling thread when lat is NULL). */
+const char* lq_last_error(const lq_lattice* lat);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LQFIRE_H */

@@ -1,0 +1,504 @@
+// Host side of liblqfire: the extern "C" entry points of lqfire.h.
+//
+// The handle owns the geometry tables on the device (neighbour masks, tile
+// flags, anchoring sums) and small scratch for the energy sum.  The caller
+// owns every field buffer and the FIRE workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lq_internal.h"
+
+using namespace lq;
+
+struct lq_lattice {
+    lq_params p{};
+    double S0 = NAN;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool l23 = false;
+    int64_t N = 0;
+    int64_t n_sim = 0;
+    // device geometry
+    uint8_t* d_mask = nullptr;
+    uint8_t* d_tile = nullptr;
+    int32_t* d_anch_site = nullptr;
+    double* d_anch_data = nullptr;
+    int n_anch = 0;
+    // energy scratch
+    double* d_epart = nullptr;
+    EnergyOut* d_eout = nullptr;
+    uint32_t* d_eticket = nullptr;
+    EnergyOut* h_eout = nullptr;  // pinned
+    // FIRE binding
+    bool bound = false;
+    void* q = nullptr;
+    void* v = nullptr;
+    void* F = nullptr;
+    Bufs<double> b64{};
+    Bufs<float> b32{};
+    double* d_partials = nullptr;
+    FireDev* d_state = nullptr;
+    FireDev* h_state = nullptr;  // pinned
+    LatDev dev{};
+    std::string err;
+};
+
+static thread_local std::string g_err;
+
+static int fail(lq_lattice* lat, int code, const std::string& msg) {
+    if (lat) lat->err = msg;
+    else g_err = msg;
+    return code;
+}
+
+#define HIPCHK(lat, expr)                                                                 \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(lat, LQ_EHIP, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static size_t elem_size(const lq_lattice* lat) { return lat->p.prec == LQ_F64 ? 8 : 4; }
+
+static int check_params(const lq_params* p, std::string& err) {
+    if (!p) {
+        err = "params is NULL";
+        return LQ_EINVAL;
+    }
+    for (int k = 0; k < 3; ++k) {
+        if (p->n[k] < 1 || p->n[k] > (1 << 20)) {
+            err = "lattice size out of range";
+            return LQ_EINVAL;
+        }
+        if (p->periodic[k] != 0 && p->periodic[k] != 1) {
+            err = "periodic flags must be 0 or 1";
+            return LQ_EINVAL;
+        }
+        if (p->periodic[k] && p->n[k] < 3) {
+            err = "a periodic axis needs at least 3 sites";
+            return LQ_EINVAL;
+        }
+    }
+    const double N = (double)p->n[0] * (double)p->n[1] * (double)p->n[2];
+    if (N > 2147483647.0) {
+        err = "more than 2^31 - 1 sites";
+        return LQ_EINVAL;
+    }
+    if (p->prec != LQ_F64 && p->prec != LQ_F32) {
+        err = "prec must be LQ_F64 or LQ_F32";
+        return LQ_EINVAL;
+    }
+    const double c[] = {p->A, p->B, p->C, p->L1, p->L2, p->L3, p->L4, p->L6};
+    for (double x : c)
+        if (!std::isfinite(x)) {
+            err = "non-finite constant";
+            return LQ_EINVAL;
+        }
+    if (p->L4 != 0.0 || p->L6 != 0.0) {
+        err = "L4 and L6 terms are not built";
+        return LQ_EUNSUPPORTED;
+    }
+    return LQ_OK;
+}
+
+static double bulk_S0(const lq_params& p) {
+    double disc = p.B * p.B - 24.0 * p.A * p.C;
+    if (!(p.C > 0.0) || disc < 0.0) return NAN;
+    return (-p.B + std::sqrt(disc)) / (6.0 * p.C);
+}
+
+static int check_dev_ptr(lq_lattice* lat, const void* ptr, const char* name) {
+    if (!ptr) return fail(lat, LQ_EINVAL, std::string(name) + " is NULL");
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(lat, LQ_EINVAL, std::string(name) + " is not a device pointer");
+    }
+    if (a.type != hipMemoryTypeDevice || a.device != lat->device)
+        return fail(lat, LQ_EINVAL, std::string(name) + " is not device memory of the lattice's device");
+    return LQ_OK;
+}
+
+// z-chunk per block: as long as possible while the grid keeps >= 2048 blocks
+static int pick_zc(const lq_params& p) {
+    const char* env = std::getenv("LQ_ZC");
+    if (env) {
+        int z = std::atoi(env);
+        if (z >= 1 && z <= 4096) return z;
+    }
+    int64_t ntx = (p.n[0] + TX - 1) / TX, nty = (p.n[1] + TY - 1) / TY;
+    int zc = 32;
+    while (zc > 4 && ntx * nty * ((p.n[2] + zc - 1) / zc) < 2048) zc /= 2;
+    return zc;
+}
+
+static void tile_flags(const lq_params& p, const std::vector<uint8_t>& mask, int zc, int ntx, int nty,
+                       int ntz, std::vector<uint8_t>& out) {
+    const int64_t nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    out.assign((size_t)ntx * nty * ntz, 0);
+    auto wrap = [](int64_t g, int64_t n, bool per) -> int64_t {
+        if (g >= 0 && g < n) return g;
+        if (!per) return -1;
+        g %= n;
+        return g < 0 ? g + n : g;
+    };
+    for (int bz = 0; bz < ntz; ++bz)
+        for (int by = 0; by < nty; ++by)
+            for (int bx = 0; bx < ntx; ++bx) {
+                bool ok = true;
+                const int64_t z0 = (int64_t)bz * zc, zc_eff = std::min<int64_t>(zc, nz - z0);
+                for (int64_t z = z0 - 1; ok && z <= z0 + zc_eff; ++z) {
+                    int64_t wz = wrap(z, nz, p.periodic[2]);
+                    if (wz < 0) { ok = false; break; }
+                    for (int64_t y = (int64_t)by * TY - 1; ok && y <= (int64_t)by * TY + TY; ++y) {
+                        int64_t wy = wrap(y, ny, p.periodic[1]);
+                        if (wy < 0) { ok = false; break; }
+                        for (int64_t x = (int64_t)bx * TX - 1; x <= (int64_t)bx * TX + TX; ++x) {
+                            int64_t wx = wrap(x, nx, p.periodic[0]);
+                            if (wx < 0 || mask[wx + nx * (wy + ny * wz)] != M_FULL) { ok = false; break; }
+                        }
+                    }
+                }
+                out[bx + (size_t)ntx * (by + (size_t)nty * bz)] = ok ? 1 : 0;
+            }
+}
+
+static void free_geometry(lq_lattice* lat) {
+    if (lat->d_mask) (void)hipFree(lat->d_mask);
+    if (lat->d_tile) (void)hipFree(lat->d_tile);
+    if (lat->d_anch_site) (void)hipFree(lat->d_anch_site);
+    if (lat->d_anch_data) (void)hipFree(lat->d_anch_data);
+    lat->d_mask = lat->d_tile = nullptr;
+    lat->d_anch_site = nullptr;
+    lat->d_anch_data = nullptr;
+}
+
+// Uploads a rasterized geometry and refreshes the device view.
+static int upload_geometry(lq_lattice* lat, const Geometry& g) {
+    HIPCHK(lat, hipSetDevice(lat->device));
+    HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    free_geometry(lat);
+    const lq_params& p = lat->p;
+    LatDev& d = lat->dev;
+    d.nx = (int)p.n[0]; d.ny = (int)p.n[1]; d.nz = (int)p.n[2];
+    for (int k = 0; k < 3; ++k) d.per[k] = p.periodic[k];
+    d.N = lat->N;
+    d.A = p.A; d.B = p.B; d.C = p.C; d.L1 = p.L1; d.L2 = p.L2; d.L3 = p.L3;
+    d.zc = pick_zc(p);
+    d.ntx = (int)((p.n[0] + TX - 1) / TX);
+    d.nty = (int)((p.n[1] + TY - 1) / TY);
+    d.ntz = (int)((p.n[2] + d.zc - 1) / d.zc);
+    std::vector<uint8_t> tiles;
+    tile_flags(p, g.mask, d.zc, d.ntx, d.nty, d.ntz, tiles);
+    HIPCHK(lat, hipMalloc(&lat->d_mask, (size_t)lat->N));
+    HIPCHK(lat, hipMemcpy(lat->d_mask, g.mask.data(), (size_t)lat->N, hipMemcpyHostToDevice));
+    HIPCHK(lat, hipMalloc(&lat->d_tile, tiles.size()));
+    HIPCHK(lat, hipMemcpy(lat->d_tile, tiles.data(), tiles.size(), hipMemcpyHostToDevice));
+    lat->n_anch = (int)g.anch_site.size();
+    if (lat->n_anch > 0) {
+        std::vector<int32_t> s32(g.anch_site.begin(), g.anch_site.end());
+        HIPCHK(lat, hipMalloc(&lat->d_anch_site, s32.size() * sizeof(int32_t)));
+        HIPCHK(lat, hipMemcpy(lat->d_anch_site, s32.data(), s32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPCHK(lat, hipMalloc(&lat->d_anch_data, g.anch_data.size() * sizeof(double)));
+        HIPCHK(lat, hipMemcpy(lat->d_anch_data, g.anch_data.data(), g.anch_data.size() * sizeof(double),
+                              hipMemcpyHostToDevice));
+    }
+    d.mask = lat->d_mask;
+    d.tile_bulk = lat->d_tile;
+    d.n_anch = lat->n_anch;
+    d.anch_site = lat->d_anch_site;
+    d.anch_data = lat->d_anch_data;
+    lat->n_sim = g.n_sim;
+    lat->bound = false;
+    return LQ_OK;
+}
+
+extern "C" {
+
+int lq_lattice_create(const lq_params* p, void* stream, lq_lattice** out) {
+    std::string err;
+    if (!out) return fail(nullptr, LQ_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_params(p, err);
+    if (rc != LQ_OK) return fail(nullptr, rc, err);
+    lq_lattice* lat = new lq_lattice();
+    lat->p = *p;
+    lat->S0 = bulk_S0(*p);
+    lat->stream = (hipStream_t)stream;
+    lat->l23 = p->L2 != 0.0 || p->L3 != 0.0;
+    lat->N = p->n[0] * p->n[1] * p->n[2];
+    hipError_t e = hipGetDevice(&lat->device);
+    if (e != hipSuccess) {
+        delete lat;
+        return fail(nullptr, LQ_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    Geometry g;
+    rc = rasterize(lat->p, lat->S0, nullptr, 0, nullptr, 0, nullptr, 0, g, err);
+    if (rc == LQ_OK) rc = upload_geometry(lat, g);
+    if (rc == LQ_OK) {
+        const int64_t nb = std::max<int64_t>(n_energy_blocks(lat->dev), 1);
+        if (hipMalloc(&lat->d_epart, (size_t)nb * 4 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&lat->d_eout, sizeof(EnergyOut)) != hipSuccess ||
+            hipMalloc(&lat->d_eticket, 256) != hipSuccess ||
+            hipHostMalloc(&lat->h_eout, sizeof(EnergyOut), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&lat->h_state, sizeof(FireDev), hipHostMallocDefault) != hipSuccess ||
+            hipMemset(lat->d_eticket, 0, 256) != hipSuccess) {
+            (void)hipGetLastError();
+            err = "device allocation failed";
+            rc = LQ_ENOMEM;
+        }
+    } else if (err.empty()) {
+        err = lat->err;
+    }
+    if (rc != LQ_OK) {
+        lq_lattice_destroy(lat);
+        return fail(nullptr, rc, err);
+    }
+    *out = lat;
+    return LQ_OK;
+}
+
+int lq_lattice_destroy(lq_lattice* lat) {
+    if (!lat) return LQ_OK;
+    (void)hipSetDevice(lat->device);
+    (void)hipStreamSynchronize(lat->stream);
+    free_geometry(lat);
+    if (lat->d_epart) (void)hipFree(lat->d_epart);
+    if (lat->d_eout) (void)hipFree(lat->d_eout);
+    if (lat->d_eticket) (void)hipFree(lat->d_eticket);
+    if (lat->h_eout) (void)hipHostFree(lat->h_eout);
+    if (lat->h_state) (void)hipHostFree(lat->h_state);
+    delete lat;
+    return LQ_OK;
+}
+
+double lq_bulk_S0(const lq_lattice* lat) { return lat ? lat->S0 : NAN; }
+
+int lq_rasterize(const lq_params* p, const lq_object* objs, int32_t n_objs, const lq_site_anchor* recs,
+                 int64_t n_recs, const int64_t* object_sites, int64_t n_object_sites, uint8_t* types,
+                 int64_t* n_anchored, int64_t* anch_site, double* anch_data, int64_t cap) {
+    std::string err;
+    int rc = check_params(p, err);
+    if (rc != LQ_OK) return fail(nullptr, rc, err);
+    if (cap < 0 || (cap > 0 && (!anch_site || !anch_data)))
+        return fail(nullptr, LQ_EINVAL, "bad output arrays");
+    Geometry g;
+    rc = rasterize(*p, bulk_S0(*p), objs, n_objs, recs, n_recs, object_sites, n_object_sites, g, err);
+    if (rc != LQ_OK) return fail(nullptr, rc, err);
+    if (types) std::memcpy(types, g.type.data(), g.type.size());
+    if (n_anchored) *n_anchored = (int64_t)g.anch_site.size();
+    const int64_t n = std::min<int64_t>(cap, (int64_t)g.anch_site.size());
+    for (int64_t i = 0; i < n; ++i) {
+        anch_site[i] = g.anch_site[i];
+        std::memcpy(anch_data + 7 * i, &g.anch_data[7 * i], 7 * sizeof(double));
+    }
+    return LQ_OK;
+}
+
+int lq_set_boundaries(lq_lattice* lat, const lq_object* objs, int32_t n_objs, const lq_site_anchor* recs,
+                      int64_t n_recs, const int64_t* object_sites, int64_t n_object_sites) {
+    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
+    std::string err;
+    Geometry g;
+    int rc = rasterize(lat->p, lat->S0, objs, n_objs, recs, n_recs, object_sites, n_object_sites, g, err);
+    if (rc != LQ_OK) return fail(lat, rc, err);
+    return upload_geometry(lat, g);
+}
+
+int lq_set_uniaxial(lq_lattice* lat, const double* directors, double S, void* q) {
+    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
+    if (!std::isfinite(S)) return fail(lat, LQ_EINVAL, "S is not finite");
+    int rc = check_dev_ptr(lat, directors, "directors");
+    if (rc == LQ_OK) rc = check_dev_ptr(lat, q, "q");
+    if (rc != LQ_OK) return rc;
+    HIPCHK(lat, hipSetDevice(lat->device));
+    rc = launch_uniaxial(lat->dev, lat->p.prec, directors, S, q, lat->stream);
+    if (rc != LQ_OK) return fail(lat, rc, "kernel launch failed");
+    return LQ_OK;
+}
+
+int lq_compute_forces(lq_lattice* lat, const void* q, void* F) {
+    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
+    int rc = check_dev_ptr(lat, q, "q");
+    if (rc == LQ_OK) rc = check_dev_ptr(lat, F, "F");
+    if (rc != LQ_OK) return rc;
+    if (q == F) return fail(lat, LQ_EINVAL, "q and F must not alias");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    rc = launch_forces(lat->dev, lat->l23, lat->p.prec, q, F, lat->stream);
+    if (rc != LQ_OK) return fail(lat, rc, "kernel launch failed");
+    return LQ_OK;
+}
+
+int lq_energy(lq_lattice* lat, const void* q, lq_energy_terms* out) {
+    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
+    if (!out) return fail(lat, LQ_EINVAL, "out is NULL");
+    int rc = check_dev_ptr(lat, q, "q");
+    if (rc != LQ_OK) return rc;
+    HIPCHK(lat, hipSetDevice(lat->device));
+    rc = launch_energy(lat->dev, lat->l23, lat->p.prec, q, lat->d_epart, lat->d_eout, lat->d_eticket,
+                       lat->stream);
+    if (rc != LQ_OK) return fail(lat, rc, "kernel launch failed");
+    HIPCHK(lat, hipMemcpyAsync(lat->h_eout, lat->d_eout, sizeof(EnergyOut), hipMemcpyDeviceToHost, lat->stream));
+    HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    out->bulk = lat->h_eout->bulk;
+    out->elastic = lat->h_eout->elastic;
+    out->anchoring = lat->h_eout->anch;
+    out->total = out->bulk + out->elastic + out->anchoring;
+    out->n_sim = lat->n_sim;
+    return LQ_OK;
+}
+
+static int64_t partial_slots(const lq_lattice* lat) {
+    return std::max<int64_t>(n_step_blocks(lat->dev), n_energy_blocks(lat->dev));
+}
+
+static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+int64_t lq_workspace_bytes(const lq_lattice* lat) {
+    if (!lat) return -1;
+    const int64_t field = align256(5 * lat->N * (int64_t)elem_size(lat));
+    return 3 * field + align256(partial_slots(lat) * 4 * (int64_t)sizeof(double)) +
+           align256((int64_t)sizeof(FireDev));
+}
+
+static int check_fire_params(lq_lattice* lat, const lq_fire_params* fp) {
+    if (!fp) return fail(lat, LQ_EINVAL, "FIRE params is NULL");
+    const double v[] = {fp->dt0, fp->dt_max, fp->alpha0, fp->f_inc, fp->f_dec, fp->f_alpha, fp->force_tol};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(lat, LQ_EINVAL, "non-finite FIRE parameter");
+    if (!(fp->dt0 > 0.0) || !(fp->dt_max > 0.0) || fp->alpha0 < 0.0 || fp->alpha0 > 1.0 ||
+        !(fp->f_inc >= 1.0) || !(fp->f_dec > 0.0) || !(fp->f_dec <= 1.0) || !(fp->f_alpha > 0.0) ||
+        fp->f_alpha > 1.0 || fp->n_min < 0 || fp->force_tol < 0.0 || fp->max_steps < 0)
+        return fail(lat, LQ_EINVAL, "FIRE parameter out of range");
+    return LQ_OK;
+}
+
+int lq_fire_init(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F, void* workspace,
+                 int64_t workspace_bytes, const lq_fire_report* resume) {
+    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
+    lat->bound = false;
+    int rc = check_fire_params(lat, fp);
+    if (rc == LQ_OK) rc = check_dev_ptr(lat, q, "q");
+    if (rc == LQ_OK) rc = check_dev_ptr(lat, v, "v");
+    if (rc == LQ_OK) rc = check_dev_ptr(lat, F, "F");
+    if (rc == LQ_OK) rc = check_dev_ptr(lat, workspace, "workspace");
+    if (rc != LQ_OK) return rc;
+    if (q == v || q == F || v == F) return fail(lat, LQ_EINVAL, "q, v and F must be distinct buffers");
+    if (workspace_bytes < lq_workspace_bytes(lat))
+        return fail(lat, LQ_ENOMEM, "workspace smaller than lq_workspace_bytes()");
+    if (((uintptr_t)workspace & 255) != 0) return fail(lat, LQ_EINVAL, "workspace must be 256-byte aligned");
+    if (resume) {
+        if (!(resume->dt > 0.0) || !std::isfinite(resume->dt) || !(resume->alpha >= 0.0) ||
+            !(resume->alpha <= 1.0) || resume->step < 0 || resume->n_pos < 0 || resume->restarts < 0)
+            return fail(lat, LQ_EINVAL, "bad resume state");
+    }
+    HIPCHK(lat, hipSetDevice(lat->device));
+    const int64_t field = align256(5 * lat->N * (int64_t)elem_size(lat));
+    char* ws = (char*)workspace;
+    void* q1 = ws;
+    void* v1 = ws + field;
+    void* F1 = ws + 2 * field;
+    lat->d_partials = (double*)(ws + 3 * field);
+    lat->d_state = (FireDev*)(ws + 3 * field + align256(partial_slots(lat) * 4 * (int64_t)sizeof(double)));
+    lat->q = q;
+    lat->v = v;
+    lat->F = F;
+    lat->b64 = Bufs<double>{{(double*)q, (double*)q1}, {(double*)v, (double*)v1}, {(double*)F, (double*)F1}};
+    lat->b32 = Bufs<float>{{(float*)q, (float*)q1}, {(float*)v, (float*)v1}, {(float*)F, (float*)F1}};
+
+    rc = launch_forces(lat->dev, lat->l23, lat->p.prec, q, F, lat->stream);
+    if (rc == LQ_OK && !resume) rc = launch_fill_zero(v, 5 * lat->N * (int64_t)elem_size(lat), lat->stream);
+    if (rc != LQ_OK) return fail(lat, rc, "kernel launch failed");
+    FireDev& s = *lat->h_state;
+    std::memset(&s, 0, sizeof(FireDev));
+    s.dt = resume ? resume->dt : fp->dt0;
+    s.alpha = resume ? resume->alpha : fp->alpha0;
+    s.c_v = 1.0;
+    s.c_F = 0.0;
+    s.n_pos = resume ? resume->n_pos : 0;
+    s.step = resume ? resume->step : 0;
+    s.restarts = resume ? resume->restarts : 0;
+    s.stop_at = s.step;
+    s.cur = 0;
+    s.done = 0;
+    s.status = LQ_RUNNING;
+    s.init_pending = 1;
+    s.dt_max = fp->dt_max;
+    s.alpha0 = fp->alpha0;
+    s.f_inc = fp->f_inc;
+    s.f_dec = fp->f_dec;
+    s.f_alpha = fp->f_alpha;
+    s.tol = fp->force_tol;
+    s.n_min = fp->n_min;
+    s.max_steps = fp->max_steps;
+    s.ticket = 0;
+    HIPCHK(lat, hipMemcpyAsync(lat->d_state, &s, sizeof(FireDev), hipMemcpyHostToDevice, lat->stream));
+    rc = launch_fire_init_reduce(lat->dev, lat->p.prec, F, v, lat->d_partials, lat->d_state, lat->stream);
+    if (rc != LQ_OK) return fail(lat, rc, "kernel launch failed");
+    HIPCHK(lat, hipMemcpyAsync(lat->h_state, lat->d_state, sizeof(FireDev), hipMemcpyDeviceToHost, lat->stream));
+    HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    lat->bound = true;
+    if (lat->h_state->status == LQ_NONFINITE) return fail(lat, LQ_ENONFINITE, "initial forces are not finite");
+    return LQ_OK;
+}
+
+static void fill_report(const FireDev& s, lq_fire_report* out) {
+    if (!out) return;
+    out->step = s.step;
+    out->n_pos = s.n_pos;
+    out->restarts = s.restarts;
+    out->status = s.status;
+    out->pad = 0;
+    out->dt = s.dt;
+    out->alpha = s.alpha;
+    out->P = s.P;
+    out->normF = std::sqrt(s.nF2);
+    out->normv = std::sqrt(s.nv2);
+    out->maxF = s.maxF;
+}
+
+int lq_fire_step(lq_lattice* lat, int64_t n_steps, lq_fire_report* out) {
+    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
+    if (!lat->bound) return fail(lat, LQ_ESTATE, "lq_fire_init has not bound buffers to this lattice");
+    if (n_steps < 0) return fail(lat, LQ_EINVAL, "n_steps < 0");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    const void* bufs = lat->p.prec == LQ_F64 ? (const void*)&lat->b64 : (const void*)&lat->b32;
+    int rc = launch_begin(lat->d_state, n_steps, lat->stream);
+    if (rc == LQ_OK) rc = launch_fire_steps(lat->dev, lat->l23, lat->p.prec, bufs, lat->d_partials, lat->d_state,
+                                            n_steps, lat->stream);
+    if (rc == LQ_OK) rc = launch_finalize(lat->dev, lat->p.prec, bufs, lat->d_state, lat->stream);
+    if (rc != LQ_OK) return fail(lat, rc, "kernel launch failed");
+    HIPCHK(lat, hipMemcpyAsync(lat->h_state, lat->d_state, sizeof(FireDev), hipMemcpyDeviceToHost, lat->stream));
+    HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    fill_report(*lat->h_state, out);
+    if (lat->h_state->status == LQ_NONFINITE) return fail(lat, LQ_ENONFINITE, "a FIRE reduction is not finite");
+    return LQ_OK;
+}
+
+int lq_minimize(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F, void* workspace,
+                int64_t workspace_bytes, lq_fire_report* out) {
+    int rc = lq_fire_init(lat, fp, q, v, F, workspace, workspace_bytes, nullptr);
+    if (rc != LQ_OK) return rc;
+    lq_fire_report r{};
+    fill_report(*lat->h_state, &r);
+    int64_t chunk = 64;
+    while (r.status == LQ_RUNNING) {
+        rc = lq_fire_step(lat, std::min<int64_t>(chunk, fp->max_steps - r.step), &r);
+        if (rc != LQ_OK) break;
+        chunk = std::min<int64_t>(chunk * 2, 1024);
+    }
+    if (out) *out = r;
+    return rc;
+}
+
+const char* lq_last_error(const lq_lattice* lat) { return lat ? lat->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"

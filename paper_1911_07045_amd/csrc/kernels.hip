@@ -1,0 +1,881 @@
+// HIP kernels of liblqfire for gfx950: the discrete Landau-de Gennes force,
+// the fused force + FIRE step, the FIRE controller, the energy and helpers.
+//
+// The energy is the paper's discretization (sec. III.B): bulk Eq. (fphase),
+// distortion Eq. (fdistortionFull) (L4 = L6 = 0) from one-sided differences
+// Eq. (onesidedderivatives) averaged over every allowed forward/backward
+// choice per axis, plus Nobili-Durand anchoring (sec. II.D).  Because the
+// choices on different axes are independent, the average factorizes:
+//   - products of differences along one axis k average to the mean over the
+//     allowed choices of that axis, which turns the L1 term and the same-axis
+//     part of L2/L3 into bond sums, bond (x, x+e_k) weighted
+//     w = 1/n_k(x) + 1/n_k(x+e_k) with n_k the number of allowed choices;
+//   - products of differences along two different axes j != k average to
+//     C_j C_k, with C_k the mean of the allowed one-sided differences of
+//     axis k (a central difference in the bulk).
+// The forces are the exact negative gradient of that energy with respect to
+// the five components q (sec. III.B), i.e. P^T applied to dE/dQ where
+// P^T G = (Gxx - Gzz, Gxy + Gyx, Gxz + Gzx, Gyy - Gzz, Gyz + Gzy).
+//
+// FIRE (Algorithm 1) is fused with the force: the kernel of step t reads
+// q, v, F of step t-1 with the steering coefficients (c_v, c_F) and dt
+// decided by the controller of step t-1, applies steering, the first half
+// kick and the drift to every site it needs (its tile plus a one-site halo,
+// recomputed in LDS), evaluates the force at the new positions, applies the
+// second half kick and writes q, v, F to the other buffer.  Per-block FP64
+// partial sums of F.v, |F|^2, |v|^2 and max|F_i| are combined by the last
+// block to finish (atomic ticket), which then runs the controller.  The host
+// never waits between steps.
+//
+// Layout: SoA fields [5][nz][ny][nx].  A block owns a TX x TY column tile and
+// marches ZC planes along z, keeping four planes of updated q (with halo) in
+// LDS so that one barrier per plane suffices.
+#include <hip/hip_runtime.h>
+
+#include "lq_internal.h"
+
+namespace lq {
+
+constexpr int PX = TX + 2;
+constexpr int PY = TY + 2;
+constexpr int NSLOT = 4;
+constexpr int RING = 2 * PX + 2 * (PY - 2);
+
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+
+__device__ __forceinline__ int wrapc(int g, int n, int per) {
+    if (g >= 0 && g < n) return g;
+    if (!per) return -1;
+    g %= n;
+    return g < 0 ? g + n : g;
+}
+
+__device__ __forceinline__ bool has_nb(uint32_t m, int k, int s) {
+    return (m >> (2 * k + (s < 0 ? 1 : 0))) & 1u;
+}
+
+__device__ __forceinline__ int n_choices(uint32_t m, int k) {
+    return (int)((m >> (2 * k)) & 1u) + (int)((m >> (2 * k + 1)) & 1u);
+}
+
+// Coefficients of C_k(x) = ap Q(x+e_k) + a0 Q(x) + am Q(x-e_k): the mean of
+// the allowed one-sided differences along axis k.
+template <typename T>
+__device__ __forceinline__ void mean_diff_coef(uint32_t m, int k, T& ap, T& a0, T& am) {
+    bool p = has_nb(m, k, +1), n = has_nb(m, k, -1);
+    if (p && n) {
+        ap = T(0.5); a0 = T(0); am = T(-0.5);
+    } else if (p) {
+        ap = T(1); a0 = T(-1); am = T(0);
+    } else if (n) {
+        ap = T(0); a0 = T(1); am = T(-1);
+    } else {
+        ap = T(0); a0 = T(0); am = T(0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void full_of(const T q[5], T Q[3][3]) {
+    Q[0][0] = q[0]; Q[0][1] = q[1]; Q[0][2] = q[2];
+    Q[1][0] = q[1]; Q[1][1] = q[3]; Q[1][2] = q[4];
+    Q[2][0] = q[2]; Q[2][1] = q[4]; Q[2][2] = -q[0] - q[3];
+}
+
+template <typename T>
+__device__ __forceinline__ void pT(const T G[3][3], T g[5]) {
+    g[0] = G[0][0] - G[2][2];
+    g[1] = G[0][1] + G[1][0];
+    g[2] = G[0][2] + G[2][0];
+    g[3] = G[1][1] - G[2][2];
+    g[4] = G[1][2] + G[2][1];
+}
+
+// d(bulk)/dq: P^T (A Q + B Q^2 + C tr(Q^2) Q)
+template <typename T>
+__device__ __forceinline__ void bulk_grad(const T q[5], T A, T B, T C, T g[5]) {
+    T Q[3][3];
+    full_of(q, Q);
+    T t2 = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) t2 = fma_t(Q[i][j], Q[i][j], t2);
+    T G[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            T qq = Q[a][0] * Q[0][b] + Q[a][1] * Q[1][b] + Q[a][2] * Q[2][b];
+            G[a][b] = (A + C * t2) * Q[a][b] + B * qq;
+        }
+    pT(G, g);
+}
+
+// The bond (L1) metric: sum_ij dQ_ij^2 = d^T M d; returns M d.
+template <typename T>
+__device__ __forceinline__ void metric(const T d[5], T o[5]) {
+    o[0] = T(2) * d[0] + d[3];
+    o[1] = T(2) * d[1];
+    o[2] = T(2) * d[2];
+    o[3] = d[0] + T(2) * d[3];
+    o[4] = T(2) * d[4];
+}
+
+// Same-axis part of L2/L3 along axis j: sum_i dQ_ij^2 (column j of dQ);
+// returns its gradient / 2 with respect to d.
+template <typename T>
+__device__ __forceinline__ void column_metric(int j, const T d[5], T o[5]) {
+    if (j == 0) {
+        o[0] = d[0]; o[1] = d[1]; o[2] = d[2]; o[3] = T(0); o[4] = T(0);
+    } else if (j == 1) {
+        o[0] = T(0); o[1] = d[1]; o[2] = T(0); o[3] = d[3]; o[4] = d[4];
+    } else {
+        T s = d[0] + d[3];
+        o[0] = s; o[1] = T(0); o[2] = d[2]; o[3] = s; o[4] = d[4];
+    }
+}
+
+// h_j = P^T H_j with H_j,ab = sum_{k != j} [L2 delta_bj C_k,ak + L3 delta_bk C_k,aj]:
+// the derivative of the cross-axis L2/L3 energy of one site with respect to
+// its mean difference C_j, mapped to q components.
+template <typename T>
+__device__ __forceinline__ void cross_h(int j, const T Ck[3][5], T L2, T L3, T h[5]) {
+    T H[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) H[a][b] = T(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k == j) continue;
+        T C[3][3];
+        full_of(Ck[k], C);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            H[a][j] += L2 * C[a][k];
+            H[a][k] += L3 * C[a][j];
+        }
+    }
+    pT(H, h);
+}
+
+// ---------------------------------------------------------------------------
+// Stencil over the LDS planes.  Offsets (dx, dy, dz) in {-1, 0, 1}; the
+// centre is (tx+1, ty+1) of the middle slot.
+template <typename T>
+struct Planes {
+    T (*q)[5][PY][PX];
+    uint8_t (*m)[PY][PX];
+    int s[3];  // slots of planes z-1, z, z+1
+    int cx, cy;
+    bool bulk;
+    __device__ __forceinline__ T at(int dx, int dy, int dz, int c) const {
+        return q[s[dz + 1]][c][cy + dy][cx + dx];
+    }
+    __device__ __forceinline__ uint32_t mask(int dx, int dy, int dz) const {
+        return bulk ? (uint32_t)M_FULL : (uint32_t)m[s[dz + 1]][cy + dy][cx + dx];
+    }
+    __device__ __forceinline__ void load5(int dx, int dy, int dz, T o[5]) const {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) o[c] = at(dx, dy, dz, c);
+    }
+};
+
+__device__ __forceinline__ void unit(int k, int s, int& dx, int& dy, int& dz) {
+    dx = k == 0 ? s : 0;
+    dy = k == 1 ? s : 0;
+    dz = k == 2 ? s : 0;
+}
+
+// mean differences C_k (k != skip) at offset o of the stencil
+template <typename T>
+__device__ __forceinline__ void mean_diffs(const Planes<T>& P, int ox, int oy, int oz, int skip,
+                                           uint32_t m, T Ck[3][5]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k == skip) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Ck[k][c] = T(0);
+            continue;
+        }
+        T ap, a0, am;
+        mean_diff_coef(m, k, ap, a0, am);
+        int ex, ey, ez;
+        unit(k, 1, ex, ey, ez);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            T v = a0 * P.at(ox, oy, oz, c);
+            if (ap != T(0)) v = fma_t(ap, P.at(ox + ex, oy + ey, oz + ez, c), v);
+            if (am != T(0)) v = fma_t(am, P.at(ox - ex, oy - ey, oz - ez, c), v);
+            Ck[k][c] = v;
+        }
+    }
+}
+
+// -dE/dq at the stencil centre (a simulated site with mask m0).
+template <typename T, bool L23>
+__device__ __forceinline__ void site_force(const Planes<T>& P, uint32_t m0, const LatDev& L,
+                                           int64_t site, T F[5]) {
+    const T A = T(L.A), B = T(L.B), C = T(L.C), L1 = T(L.L1);
+    T q0[5];
+    P.load5(0, 0, 0, q0);
+    T g[5];
+    bulk_grad(q0, A, B, C, g);
+    // bond sums: L1 and the same-axis part of L2/L3
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int s = -1; s <= 1; s += 2) {
+            if (!has_nb(m0, k, s)) continue;
+            int dx, dy, dz;
+            unit(k, s, dx, dy, dz);
+            uint32_t mn = P.mask(dx, dy, dz);
+            T w = (n_choices(m0, k) == 2 ? T(0.5) : T(1)) + (n_choices(mn, k) == 2 ? T(0.5) : T(1));
+            T d[5], o[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) d[c] = q0[c] - P.at(dx, dy, dz, c);
+            metric(d, o);
+            T wl = w * L1;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) g[c] = fma_t(wl, o[c], g[c]);
+            if (L23) {
+                column_metric(k, d, o);
+                T wl23 = w * (T(L.L2) + T(L.L3));
+#pragma unroll
+                for (int c = 0; c < 5; ++c) g[c] = fma_t(wl23, o[c], g[c]);
+            }
+        }
+    if (L23) {
+        const T L2 = T(L.L2), L3 = T(L.L3);
+        // cross-axis part: sum over sites x whose C_j uses Q(centre)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+#pragma unroll
+            for (int s = -1; s <= 1; s += 2) {
+                // x = centre - s e_j uses Q(centre) with coefficient a_{j,s}(x)
+                int dx, dy, dz;
+                unit(j, -s, dx, dy, dz);
+                uint32_t mx = P.mask(dx, dy, dz);
+                T ap, a0, am;
+                mean_diff_coef(mx, j, ap, a0, am);
+                T coef = s > 0 ? ap : am;
+                if (coef == T(0)) continue;
+                T Ck[3][5], h[5];
+                mean_diffs(P, dx, dy, dz, j, mx, Ck);
+                cross_h(j, Ck, L2, L3, h);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) g[c] = fma_t(coef, h[c], g[c]);
+            }
+            T ap, a0, am;
+            mean_diff_coef(m0, j, ap, a0, am);
+            if (a0 != T(0)) {
+                T Ck[3][5], h[5];
+                mean_diffs(P, 0, 0, 0, j, m0, Ck);
+                cross_h(j, Ck, L2, L3, h);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) g[c] = fma_t(a0, h[c], g[c]);
+            }
+        }
+    }
+    if (m0 & M_ANCH) {
+        // binary search of the site in the sorted anchored list
+        int lo = 0, hi = L.n_anch - 1, at = -1;
+        while (lo <= hi) {
+            int mid = (lo + hi) >> 1;
+            int64_t sv = L.anch_site[mid];
+            if (sv == site) { at = mid; break; }
+            if (sv < site) lo = mid + 1; else hi = mid - 1;
+        }
+        if (at >= 0) {
+            const double* d = L.anch_data + 7 * (int64_t)at;
+            T W = T(d[0]);
+            T qw[5] = {T(d[1]), T(d[2]), T(d[3]), T(d[4]), T(d[5])};
+            // d/dq of sum W tr((Q - Q0)^2) = P^T 2 (W Q - sum W Q0)
+            T G5[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) G5[c] = T(2) * (W * q0[c] - qw[c]);
+            T G[3][3], ga[5];
+            full_of(G5, G);
+            pT(G, ga);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) g[c] += ga[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F[c] = -g[c];
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Block reduction of 4 values (3 sums, 1 max) in a fixed order.
+__device__ __forceinline__ void block_reduce4(double r[4], double (*scratch)[4]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double a = wave_sum(r[0]), b = wave_sum(r[1]), c = wave_sum(r[2]), d = wave_max(r[3]);
+    if (lane == 0) {
+        scratch[wv][0] = a; scratch[wv][1] = b; scratch[wv][2] = c; scratch[wv][3] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int w = 0; w < nw; ++w) {
+            s0 += scratch[w][0]; s1 += scratch[w][1]; s2 += scratch[w][2];
+            s3 = fmax(s3, scratch[w][3]);
+        }
+        r[0] = s0; r[1] = s1; r[2] = s2; r[3] = s3;
+    }
+}
+
+// FIRE controller (Algorithm 1), run by one thread after the grid reduction.
+// Steering and restart decided here are applied to v by the next step kernel
+// (or by the finalize kernel) as v <- c_v v + c_F F.
+__device__ void fire_control(FireDev* st, double P, double nF2, double nv2, double maxF) {
+    st->P = P; st->nF2 = nF2; st->nv2 = nv2; st->maxF = maxF;
+    if (st->init_pending) {
+        st->init_pending = 0;
+        if (!(isfinite(nF2) && isfinite(nv2) && isfinite(maxF))) {
+            st->status = LQ_NONFINITE; st->done = 1;
+        } else if (maxF < st->tol) {
+            st->status = LQ_CONVERGED; st->done = 1;
+        } else if (st->step >= st->max_steps) {
+            st->status = LQ_MAX_STEPS; st->done = 1;
+        }
+        return;
+    }
+    st->step += 1;
+    st->cur = 1 - st->cur;
+    if (!(isfinite(P) && isfinite(nF2) && isfinite(nv2) && isfinite(maxF))) {
+        st->status = LQ_NONFINITE;
+        st->done = 1;
+        st->c_v = 1.0; st->c_F = 0.0;
+        return;
+    }
+    if (P > 0.0) {
+        double nF = sqrt(nF2), nv = sqrt(nv2);
+        st->c_v = 1.0 - st->alpha;
+        st->c_F = st->alpha * nv / nF;
+        st->n_pos += 1;
+        if (st->n_pos > st->n_min) {
+            st->dt = fmin(st->dt * st->f_inc, st->dt_max);
+            st->alpha = st->alpha * st->f_alpha;
+        }
+    } else {
+        st->c_v = 0.0; st->c_F = 0.0;
+        st->dt = st->dt * st->f_dec;
+        st->alpha = st->alpha0;
+        st->n_pos = 0;
+        st->restarts += 1;
+    }
+    if (maxF < st->tol) {
+        st->status = LQ_CONVERGED; st->done = 1;
+    } else if (st->step >= st->max_steps) {
+        st->status = LQ_MAX_STEPS; st->done = 1;
+    } else if (st->step >= st->stop_at) {
+        st->done = 1;
+    }
+}
+
+// Writes this block's partials, and in the last block to arrive reduces all
+// of them in block order and runs the controller.
+__device__ void grid_finish(double r[4], double* partials, FireDev* st, int nblocks, int bid,
+                            double (*scratch)[4], int* flag) {
+    block_reduce4(r, scratch);
+    if (threadIdx.x == 0) {
+        double* p = partials + 4 * (int64_t)bid;
+        p[0] = r[0]; p[1] = r[1]; p[2] = r[2]; p[3] = r[3];
+        __threadfence();
+        unsigned t = atomicAdd(&st->ticket, 1u);
+        *flag = (t == (unsigned)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!*flag) return;
+    __threadfence();
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        const volatile double* p = partials + 4 * (int64_t)b;
+        s[0] += p[0]; s[1] += p[1]; s[2] += p[2]; s[3] = fmax(s[3], p[3]);
+    }
+    __syncthreads();
+    block_reduce4(s, scratch);
+    if (threadIdx.x == 0) {
+        fire_control(st, s[0], s[1], s[2], s[3]);
+        st->ticket = 0;
+        __threadfence();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The z-marching kernel.  STEP = false: F = force(q) only.  STEP = true: one
+// fused FIRE step between the two buffers of b.
+template <typename T, bool L23, bool STEP>
+__global__ __launch_bounds__(NTHREADS) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
+                                                    T* __restrict__ Fout, double* partials,
+                                                    FireDev* st) {
+    __shared__ T sq[NSLOT][5][PY][PX];
+    __shared__ uint8_t sm[NSLOT][PY][PX];
+    __shared__ double scratch[NTHREADS / 64][4];
+    __shared__ int last_flag;
+
+    const int nblocks = (int)gridDim.x;
+    int bid = (int)blockIdx.x;
+    // keep neighbouring tiles on one XCD: dispatch is round-robin over 8 XCDs
+    if ((nblocks & 7) == 0) bid = (bid & 7) * (nblocks >> 3) + (bid >> 3);
+    const int bx = bid % L.ntx, by = (bid / L.ntx) % L.nty, bz = bid / (L.ntx * L.nty);
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * L.zc;
+    const bool bulk = L.tile_bulk[bid] != 0;
+    const int64_t N = L.N;
+
+    const T* q_in;
+    const T* v_in = nullptr;
+    const T* F_in = nullptr;
+    T* q_out = nullptr;
+    T* v_out = nullptr;
+    T* F_out;
+    T cv = T(1), cF = T(0), dt = T(0), hdt = T(0);
+    if (STEP) {
+        if (st->done) return;
+        const int cur = st->cur;
+        q_in = b.q[cur]; v_in = b.v[cur]; F_in = b.F[cur];
+        q_out = b.q[1 - cur]; v_out = b.v[1 - cur]; F_out = b.F[1 - cur];
+        cv = T(st->c_v); cF = T(st->c_F);
+        const double dtd = st->dt;
+        dt = T(dtd); hdt = T(0.5 * dtd);
+    } else {
+        q_in = qin;
+        F_out = Fout;
+    }
+
+    const int gx_own = x0 + tx, gy_own = y0 + ty;
+    const bool own_xy = gx_own < L.nx && gy_own < L.ny;
+    const int wx_own = wrapc(gx_own, L.nx, L.per[0]);
+    const int wy_own = wrapc(gy_own, L.ny, L.per[1]);
+
+    double red[4] = {0.0, 0.0, 0.0, 0.0};
+    T v1_prev[5], v1_cur[5];
+    uint32_t m_prev = 0, m_cur = 0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) { v1_prev[c] = T(0); v1_cur[c] = T(0); }
+
+    const int zc = min(L.zc, L.nz - z0);
+    for (int i = 0; i <= zc + 1; ++i) {
+        const int slot = i & (NSLOT - 1);
+        const int wz = wrapc(z0 - 1 + i, L.nz, L.per[2]);
+        // rotate the per-thread pipeline: v1 of the plane that will get its force next
+#pragma unroll
+        for (int c = 0; c < 5; ++c) v1_prev[c] = v1_cur[c];
+        m_prev = m_cur;
+        // own position (interior of the padded plane), then the halo ring
+        for (int r = threadIdx.x; r < NTHREADS + RING; r += NTHREADS) {
+            int px, py, wx, wy;
+            if (r < NTHREADS) {
+                px = tx + 1; py = ty + 1; wx = wx_own; wy = wy_own;
+            } else {
+                int k = r - NTHREADS;
+                if (k < PX) { px = k; py = 0; }
+                else if (k < 2 * PX) { px = k - PX; py = PY - 1; }
+                else if (k < 2 * PX + PY - 2) { px = 0; py = k - 2 * PX + 1; }
+                else { px = PX - 1; py = k - 2 * PX - (PY - 2) + 1; }
+                wx = wrapc(x0 - 1 + px, L.nx, L.per[0]);
+                wy = wrapc(y0 - 1 + py, L.ny, L.per[1]);
+            }
+            uint32_t m = 0;
+            T qn[5] = {T(0), T(0), T(0), T(0), T(0)};
+            T v1[5] = {T(0), T(0), T(0), T(0), T(0)};
+            if (wx >= 0 && wy >= 0 && wz >= 0) {
+                const int64_t s = (int64_t)wx + (int64_t)L.nx * ((int64_t)wy + (int64_t)L.ny * wz);
+                m = bulk ? (uint32_t)M_FULL : (uint32_t)L.mask[s];
+                if (m & M_SIM) {
+                    if (STEP) {
+#pragma unroll
+                        for (int c = 0; c < 5; ++c) {
+                            T q = q_in[c * N + s], v = v_in[c * N + s], f = F_in[c * N + s];
+                            T vm = fma_t(cv, v, cF * f);
+                            v1[c] = fma_t(hdt, f, vm);
+                            qn[c] = fma_t(dt, v1[c], q);
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 5; ++c) qn[c] = q_in[c * N + s];
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 5; ++c) sq[slot][c][py][px] = qn[c];
+            sm[slot][py][px] = (uint8_t)m;
+            if (r < NTHREADS) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) v1_cur[c] = v1[c];
+                m_cur = m;
+            }
+        }
+        __syncthreads();
+        if (i < 2) continue;
+        // force at plane index i-1 (global z = z0 + i - 2)
+        const int zf = z0 + i - 2;
+        if (own_xy && (m_prev & M_SIM)) {
+            Planes<T> P;
+            P.q = sq; P.m = sm;
+            P.s[0] = (i - 2) & (NSLOT - 1);
+            P.s[1] = (i - 1) & (NSLOT - 1);
+            P.s[2] = slot;
+            P.cx = tx + 1; P.cy = ty + 1;
+            P.bulk = bulk;
+            const int64_t s = (int64_t)gx_own + (int64_t)L.nx * ((int64_t)gy_own + (int64_t)L.ny * zf);
+            T F[5];
+            site_force<T, L23>(P, m_prev, L, s, F);
+            if (STEP) {
+                T qn[5];
+                P.load5(0, 0, 0, qn);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    T v2 = fma_t(hdt, F[c], v1_prev[c]);
+                    q_out[c * N + s] = qn[c];
+                    v_out[c * N + s] = v2;
+                    F_out[c * N + s] = F[c];
+                    double fd = (double)F[c], vd = (double)v2;
+                    red[0] = fma(fd, vd, red[0]);
+                    red[1] = fma(fd, fd, red[1]);
+                    red[2] = fma(vd, vd, red[2]);
+                    red[3] = fmax(red[3], fabs(fd));
+                    if (fd != fd) red[3] = fd;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) F_out[c * N + s] = F[c];
+            }
+        } else if (own_xy && zf < L.nz) {
+            // sites inside objects carry no degrees of freedom
+            const int64_t s = (int64_t)gx_own + (int64_t)L.nx * ((int64_t)gy_own + (int64_t)L.ny * zf);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                F_out[c * N + s] = T(0);
+                if (STEP) { q_out[c * N + s] = T(0); v_out[c * N + s] = T(0); }
+            }
+        }
+    }
+    if (STEP) grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
+}
+
+// ---------------------------------------------------------------------------
+// lq_fire_init reduction: |F|^2, |v|^2, F.v, max|F_i| of the initial state,
+// then the controller's initial convergence test.
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_reduce(const T* __restrict__ F, const T* __restrict__ v,
+                                                     int64_t n, double* partials, FireDev* st) {
+    __shared__ double scratch[4][4];
+    __shared__ int last_flag;
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double f = (double)F[i], w = (double)v[i];
+        r[0] = fma(f, w, r[0]);
+        r[1] = fma(f, f, r[1]);
+        r[2] = fma(w, w, r[2]);
+        r[3] = fmax(r[3], fabs(f));
+        if (f != f) r[3] = f;
+    }
+    grid_finish(r, partials, st, (int)gridDim.x, (int)blockIdx.x, scratch, &last_flag);
+}
+
+__global__ void k_begin(FireDev* st, int64_t n_steps) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (st->status == LQ_RUNNING) {
+            st->done = 0;
+            st->stop_at = st->step + n_steps;
+            if (n_steps <= 0) st->done = 1;
+        }
+    }
+}
+
+// Brings the current state into buffer 0 and applies the pending steering.
+template <typename T>
+__global__ __launch_bounds__(256) void k_finalize(Bufs<T> b, int64_t n, const FireDev* st) {
+    const int cur = st->cur;
+    const T cv = T(st->c_v), cF = T(st->c_F);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        T v = b.v[cur][i], f = b.F[cur][i];
+        T vm = fma_t(cv, v, cF * f);
+        if (cur) {
+            b.q[0][i] = b.q[1][i];
+            b.F[0][i] = f;
+        }
+        b.v[0][i] = vm;
+    }
+}
+
+__global__ void k_reset_mix(FireDev* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->cur = 0;
+        st->c_v = 1.0;
+        st->c_F = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(uint32_t* p, int64_t n_words) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// q = 3/2 S (n n - I/3) at simulated sites, 0 inside objects.  Products are
+// rounded one by one (no contraction) so that the state is reproducible.
+template <typename T>
+__global__ __launch_bounds__(256) void k_uniaxial(LatDev L, const double* __restrict__ dirs, double S,
+                                                  T* __restrict__ q) {
+#pragma clang fp contract(off)
+    const int64_t N = L.N;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        double r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (L.mask[s] & M_SIM) {
+            double nx = dirs[s], ny = dirs[N + s], nz = dirs[2 * N + s];
+            double h = 1.5 * S;
+            r[0] = h * (nx * nx - 1.0 / 3.0);
+            r[1] = h * nx * ny;
+            r[2] = h * nx * nz;
+            r[3] = h * (ny * ny - 1.0 / 3.0);
+            r[4] = h * ny * nz;
+        }
+        for (int c = 0; c < 5; ++c) q[c * N + s] = T(r[c]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Energy: one thread per site, FP64 arithmetic, per-term block partials
+// reduced in block order by the last block.
+template <typename T, bool L23>
+__global__ __launch_bounds__(256) void k_energy(LatDev L, const T* __restrict__ q, double* partials,
+                                                EnergyOut* out, uint32_t* ticket) {
+    __shared__ double scratch[4][4];
+    __shared__ int last_flag;
+    const int64_t N = L.N;
+    double e_b = 0.0, e_d = 0.0, e_a = 0.0;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t m = L.mask[s];
+        if (!(m & M_SIM)) continue;
+        const int x = (int)(s % L.nx), y = (int)((s / L.nx) % L.ny), z = (int)(s / ((int64_t)L.nx * L.ny));
+        double q0[5];
+        for (int c = 0; c < 5; ++c) q0[c] = (double)q[c * N + s];
+        double Q[3][3];
+        full_of(q0, Q);
+        double t2 = 0.0, t3 = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                t2 += Q[i][j] * Q[j][i];
+                for (int k = 0; k < 3; ++k) t3 += Q[i][j] * Q[j][k] * Q[k][i];
+            }
+        e_b += 0.5 * L.A * t2 + L.B / 3.0 * t3 + 0.25 * L.C * t2 * t2;
+        // neighbour q along each axis and direction
+        double qn[3][2][5];
+        for (int k = 0; k < 3; ++k)
+            for (int si = 0; si < 2; ++si) {
+                const int sg = si == 0 ? 1 : -1;
+                for (int c = 0; c < 5; ++c) qn[k][si][c] = 0.0;
+                if (!has_nb(m, k, sg)) continue;
+                int c3[3] = {x, y, z};
+                const int n3[3] = {L.nx, L.ny, L.nz};
+                c3[k] = wrapc(c3[k] + sg, n3[k], L.per[k]);
+                const int64_t t = (int64_t)c3[0] + (int64_t)L.nx * ((int64_t)c3[1] + (int64_t)L.ny * c3[2]);
+                for (int c = 0; c < 5; ++c) qn[k][si][c] = (double)q[c * N + t];
+            }
+        double ed = 0.0;
+        double Cm[3][5];
+        for (int k = 0; k < 3; ++k) {
+            const int nk = n_choices(m, k);
+            double acc1 = 0.0, acc23 = 0.0;
+            for (int si = 0; si < 2; ++si) {
+                if (!has_nb(m, k, si == 0 ? 1 : -1)) continue;
+                double d[5], o[5];
+                for (int c = 0; c < 5; ++c) d[c] = qn[k][si][c] - q0[c];
+                metric(d, o);
+                for (int c = 0; c < 5; ++c) acc1 += d[c] * o[c];
+                if (L23) {
+                    column_metric(k, d, o);
+                    for (int c = 0; c < 5; ++c) acc23 += d[c] * o[c];
+                }
+            }
+            if (nk > 0) {
+                ed += 0.5 * L.L1 * acc1 / nk;
+                if (L23) ed += 0.5 * (L.L2 + L.L3) * acc23 / nk;
+            }
+            double ap, a0, am;
+            mean_diff_coef(m, k, ap, a0, am);
+            for (int c = 0; c < 5; ++c)
+                Cm[k][c] = ap * qn[k][0][c] + a0 * q0[c] + am * qn[k][1][c];
+        }
+        if (L23) {
+            // sum_{j<k} L2 sum_i C_j,ij C_k,ik + L3 sum_i C_j,ik C_k,ij
+            double Cf[3][3][3];
+            for (int k = 0; k < 3; ++k) full_of(Cm[k], Cf[k]);
+            for (int j = 0; j < 3; ++j)
+                for (int k = j + 1; k < 3; ++k)
+                    for (int i = 0; i < 3; ++i)
+                        ed += L.L2 * Cf[j][i][j] * Cf[k][i][k] + L.L3 * Cf[j][i][k] * Cf[k][i][j];
+        }
+        e_d += ed;
+        if (m & M_ANCH) {
+            int lo = 0, hi = L.n_anch - 1, at = -1;
+            while (lo <= hi) {
+                int mid = (lo + hi) >> 1;
+                int64_t sv = L.anch_site[mid];
+                if (sv == s) { at = mid; break; }
+                if (sv < s) lo = mid + 1; else hi = mid - 1;
+            }
+            if (at >= 0) {
+                const double* d = L.anch_data + 7 * (int64_t)at;
+                double Qw[3][3];
+                full_of(d + 1, Qw);
+                double cross = 0.0;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) cross += Q[i][j] * Qw[i][j];
+                e_a += d[0] * t2 - 2.0 * cross + d[6];
+            }
+        }
+    }
+    double r[4] = {e_b, e_d, e_a, 0.0};
+    block_reduce4(r, scratch);
+    if (threadIdx.x == 0) {
+        double* p = partials + 4 * (int64_t)blockIdx.x;
+        p[0] = r[0]; p[1] = r[1]; p[2] = r[2]; p[3] = 0.0;
+        __threadfence();
+        unsigned t = atomicAdd(ticket, 1u);
+        last_flag = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last_flag) return;
+    __threadfence();
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+        const volatile double* p = partials + 4 * (int64_t)b;
+        s4[0] += p[0]; s4[1] += p[1]; s4[2] += p[2];
+    }
+    __syncthreads();
+    block_reduce4(s4, scratch);
+    if (threadIdx.x == 0) {
+        out->bulk = s4[0]; out->elastic = s4[1]; out->anch = s4[2];
+        *ticket = 0;
+        __threadfence();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+static int hip_status(hipError_t e) { return e == hipSuccess ? LQ_OK : LQ_EHIP; }
+
+int64_t n_step_blocks(const LatDev& L) { return (int64_t)L.ntx * L.nty * L.ntz; }
+int64_t n_energy_blocks(const LatDev& L) {
+    int64_t b = (L.N + 255) / 256;
+    return b < 2048 ? b : 2048;
+}
+
+static int grid_1d(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+int launch_forces(const LatDev& L, bool l23, int prec, const void* q, void* F, void* stream) {
+    dim3 g((unsigned)n_step_blocks(L)), blk(NTHREADS);
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == LQ_F64) {
+        Bufs<double> b{};
+        if (l23) k_march<double, true, false><<<g, blk, 0, s>>>(L, b, (const double*)q, (double*)F, nullptr, nullptr);
+        else k_march<double, false, false><<<g, blk, 0, s>>>(L, b, (const double*)q, (double*)F, nullptr, nullptr);
+    } else {
+        Bufs<float> b{};
+        if (l23) k_march<float, true, false><<<g, blk, 0, s>>>(L, b, (const float*)q, (float*)F, nullptr, nullptr);
+        else k_march<float, false, false><<<g, blk, 0, s>>>(L, b, (const float*)q, (float*)F, nullptr, nullptr);
+    }
+    return hip_status(hipGetLastError());
+}
+
+int launch_fire_steps(const LatDev& L, bool l23, int prec, const void* bufs, double* partials,
+                      FireDev* st, int64_t n_steps, void* stream) {
+    dim3 g((unsigned)n_step_blocks(L)), blk(NTHREADS);
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t i = 0; i < n_steps; ++i) {
+        if (prec == LQ_F64) {
+            const Bufs<double>& b = *(const Bufs<double>*)bufs;
+            if (l23) k_march<double, true, true><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
+            else k_march<double, false, true><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
+        } else {
+            const Bufs<float>& b = *(const Bufs<float>*)bufs;
+            if (l23) k_march<float, true, true><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
+            else k_march<float, false, true><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return LQ_EHIP;
+    }
+    return LQ_OK;
+}
+
+int launch_fire_init_reduce(const LatDev& L, int prec, const void* F, const void* v,
+                            double* partials, FireDev* st, void* stream);
+
+int launch_begin(FireDev* st, int64_t n_steps, void* stream) {
+    k_begin<<<1, 64, 0, (hipStream_t)stream>>>(st, n_steps);
+    return hip_status(hipGetLastError());
+}
+
+int launch_finalize(const LatDev& L, int prec, const void* bufs, FireDev* st, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = 5 * L.N;
+    if (prec == LQ_F64) k_finalize<double><<<grid_1d(n), 256, 0, s>>>(*(const Bufs<double>*)bufs, n, st);
+    else k_finalize<float><<<grid_1d(n), 256, 0, s>>>(*(const Bufs<float>*)bufs, n, st);
+    if (hipGetLastError() != hipSuccess) return LQ_EHIP;
+    k_reset_mix<<<1, 64, 0, s>>>(st);
+    return hip_status(hipGetLastError());
+}
+
+int launch_fill_zero(void* p, int64_t bytes, void* stream) {
+    const int64_t w = bytes / 4;
+    k_fill_zero<<<grid_1d(w), 256, 0, (hipStream_t)stream>>>((uint32_t*)p, w);
+    return hip_status(hipGetLastError());
+}
+
+int launch_energy(const LatDev& L, bool l23, int prec, const void* q, double* partials,
+                  EnergyOut* out, uint32_t* ticket, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const int g = (int)n_energy_blocks(L);
+    if (prec == LQ_F64) {
+        if (l23) k_energy<double, true><<<g, 256, 0, s>>>(L, (const double*)q, partials, out, ticket);
+        else k_energy<double, false><<<g, 256, 0, s>>>(L, (const double*)q, partials, out, ticket);
+    } else {
+        if (l23) k_energy<float, true><<<g, 256, 0, s>>>(L, (const float*)q, partials, out, ticket);
+        else k_energy<float, false><<<g, 256, 0, s>>>(L, (const float*)q, partials, out, ticket);
+    }
+    return hip_status(hipGetLastError());
+}
+
+int launch_uniaxial(const LatDev& L, int prec, const double* dirs, double S, void* q,
+                    void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == LQ_F64) k_uniaxial<double><<<grid_1d(L.N), 256, 0, s>>>(L, dirs, S, (double*)q);
+    else k_uniaxial<float><<<grid_1d(L.N), 256, 0, s>>>(L, dirs, S, (float*)q);
+    return hip_status(hipGetLastError());
+}
+
+int launch_fire_init_reduce(const LatDev& L, int prec, const void* F, const void* v,
+                            double* partials, FireDev* st, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = 5 * L.N;
+    const int g = (int)n_energy_blocks(L);
+    if (prec == LQ_F64) k_init_reduce<double><<<g, 256, 0, s>>>((const double*)F, (const double*)v, n, partials, st);
+    else k_init_reduce<float><<<g, 256, 0, s>>>((const float*)F, (const float*)v, n, partials, st);
+    return hip_status(hipGetLastError());
+}
+
+}  // namespace lq

@@ -1,0 +1,98 @@
+// Internal declarations shared by the host side of liblqfire and its kernels.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "lqfire.h"
+
+namespace lq {
+
+// Per-site neighbour mask byte.  Bits 0..5: the face neighbour +x, -x, +y,
+// -y, +z, -z exists and is simulated; bit 6: the site itself is simulated;
+// bit 7: the site carries anchoring.  Sites inside objects and positions off
+// an open edge have mask 0.
+constexpr uint8_t M_SIM = 0x40;
+constexpr uint8_t M_ANCH = 0x80;
+constexpr uint8_t M_FULL = 0x7F;  // simulated bulk site with all six neighbours
+
+// Host-side rasterization result.
+struct Geometry {
+    std::vector<uint8_t> type;       // 0 bulk, 1 boundary, 2 object
+    std::vector<uint8_t> mask;       // neighbour mask (above)
+    std::vector<int64_t> anch_site;  // sorted
+    std::vector<double> anch_data;   // 7 per anchored site
+    int64_t n_sim = 0;
+};
+
+// Returns LQ_OK or an error code with a message in err.
+int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_objs,
+              const lq_site_anchor* recs, int64_t n_recs, const int64_t* object_sites,
+              int64_t n_object_sites, Geometry& g, std::string& err);
+
+// Tile geometry of the fused kernel: TX x TY columns, each block marches
+// zc planes.
+constexpr int TX = 64;
+constexpr int TY = 4;
+constexpr int NTHREADS = TX * TY;
+
+// Device view of a lattice.
+struct LatDev {
+    int nx, ny, nz;
+    int per[3];
+    int64_t N;
+    const uint8_t* mask;
+    const uint8_t* tile_bulk;  // 1: every site of the padded tile has mask M_FULL
+    int n_anch;
+    const int32_t* anch_site;  // sorted
+    const double* anch_data;   // 7 per anchored site
+    double A, B, C, L1, L2, L3;
+    int zc, ntx, nty, ntz;
+};
+
+// FIRE state kept in device memory.
+struct FireDev {
+    double dt, alpha;
+    double c_v, c_F;  // steering still to be applied to the stored v
+    int64_t n_pos, step, restarts, stop_at;
+    int32_t cur;      // which of the two buffers holds the current state
+    int32_t done;     // no further step in this call
+    int32_t status;   // LQ_RUNNING / LQ_CONVERGED / LQ_MAX_STEPS / LQ_NONFINITE
+    int32_t init_pending;  // the next reduction is the one of lq_fire_init
+    double P, nF2, nv2, maxF;
+    double dt_max, alpha0, f_inc, f_dec, f_alpha, tol;
+    int64_t n_min, max_steps;
+    uint32_t ticket;
+    uint32_t pad2;
+};
+
+template <typename T>
+struct Bufs {
+    T* q[2];
+    T* v[2];
+    T* F[2];
+};
+
+struct EnergyOut {
+    double bulk, elastic, anch;
+};
+
+// Kernel launchers (kernels.hip).  All enqueue on stream.
+int launch_forces(const LatDev& L, bool l23, int prec, const void* q, void* F, void* stream);
+int launch_fire_init_reduce(const LatDev& L, int prec, const void* F, const void* v,
+                            double* partials, FireDev* st, void* stream);
+int launch_fire_steps(const LatDev& L, bool l23, int prec, const void* bufs, double* partials,
+                      FireDev* st, int64_t n_steps, void* stream);
+int launch_begin(FireDev* st, int64_t n_steps, void* stream);
+int launch_finalize(const LatDev& L, int prec, const void* bufs, FireDev* st, void* stream);
+int launch_fill_zero(void* p, int64_t bytes, void* stream);
+int launch_energy(const LatDev& L, bool l23, int prec, const void* q, double* partials,
+                  EnergyOut* out, uint32_t* ticket, void* stream);
+int launch_uniaxial(const LatDev& L, int prec, const double* dirs, double S, void* q,
+                    void* stream);
+int64_t n_step_blocks(const LatDev& L);
+int64_t n_energy_blocks(const LatDev& L);
+
+}  // namespace lq

@@ -56,6 +56,15 @@ def random_directors(seed: int, n_sites: int, start: int = 0) -> np.ndarray:
     return np.stack([r * np.cos(phi), r * np.sin(phi), z])
 
 
+TAG_FIELD = 3
+
+
+def random_field(seed: int, n_sites: int, scale: float = 0.3, start: int = 0) -> np.ndarray:
+    """Generic (not uniaxial) q-components, shape (5, n_sites), uniform in [-scale, scale)."""
+    u = uniform(seed, TAG_FIELD, 5 * start, 5 * n_sites).reshape(n_sites, 5).T
+    return np.ascontiguousarray(scale * (2.0 * u - 1.0))
+
+
 class _Stream:
     """Sequential draws from one (seed, tag) stream."""
 

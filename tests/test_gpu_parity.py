@@ -1,0 +1,348 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances: FP64 forces and energies to 1e-12 relative (rounding order only);
+FIRE force trajectories to 1e-10 relative per step; converged energies to
+1e-6 relative and max |dQ| < 1e-5; the FP32 form to 1e-5 relative in forces
+(float rounding of values of order one).  Inputs come from synth only.
+"""
+import numpy as np
+import pytest
+
+from paper_1911_07045_amd import lqfire, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+A, B, C = -0.172, -2.12, 1.73
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    lqfire.lib()
+
+
+def pair(ora, shape, periodic=(True, True, True), L2=0.0, L3=0.0, objects=(), records=(), osites=(),
+         prec="f64", L1=2.32):
+    p = ora.Problem(shape, periodic, L1=L1, L2=L2, L3=L3, objects=objects, site_records=records,
+                    object_sites=osites)
+    lat = lqfire.Lattice(shape, periodic, prec, L1=L1, L2=L2, L3=L3)
+    if objects or records or len(osites):
+        lat.set_boundaries(objects, records, osites)
+    return p, lat
+
+
+def to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+CASES = {
+    "bulk32_L1": dict(shape=(32, 32, 32)),
+    "ragged_periodic_L23": dict(shape=(70, 9, 13), L2=1.16, L3=0.7),
+    "open_x_L23": dict(shape=(67, 6, 10), periodic=(False, True, True), L2=1.16, L3=1.16),
+    "open_all_L1": dict(shape=(5, 7, 6), periodic=(False, False, False)),
+    "one_site_thick_open": dict(shape=(1, 5, 4), periodic=(False, True, True), L2=1.0, L3=0.4),
+    "two_site_thick_open": dict(shape=(2, 3, 3), periodic=(False, True, True), L2=0.5, L3=1.2),
+    "colloid_slab24_L23": dict(shape=(24, 24, 24), L2=1.16, L3=1.16, objects=[
+        dict(kind="wall", axis=2, plane=0, law="nd", W=0.5, dir=(1.0, 0.0, 0.0)),
+        dict(kind="wall", axis=2, plane=23, law="nd", W=0.5, dir=(1.0, 0.0, 0.0)),
+        dict(kind="sphere", center=(11.5, 11.5, 11.5), radius=5.0, law="rp", W=5.0, dir="normal")]),
+    "spheres_across_wrap_L1": dict(shape=(72, 40, 36), objects=[
+        dict(kind="sphere", center=(1.2, 38.7, 17.3), radius=6.3, law="rp", W=3.0, dir="normal"),
+        dict(kind="sphere", center=(40.0, 20.0, 35.5), radius=4.6, law="rp", W=9.0, dir="normal")]),
+    "patterned_records_L23": dict(shape=(40, 12, 9), L2=1.16, L3=1.16, objects=[
+        dict(kind="patterned_wall", axis=2, plane=0, law="rp", W=2.0, pitch=(10, 6), offset=(4.5, 2.5),
+             count=(4, 2)),
+        dict(kind="wall", axis=2, plane=8, law="rp", W=2.0, dir="normal")],
+        records=[dict(site=1000, law="nd", W=0.4, n0=(1, 2, 2)), dict(site=1000, law="rp", W=1.0, n0=(0, 0, 1))],
+        osites=[2000, 2001, 2040]),
+    "sandwiched_plane_L23": dict(shape=(66, 5, 3), L2=1.16, L3=0.3, objects=[
+        dict(kind="wall", axis=2, plane=0, law="nd", W=0.7, dir=(0.0, 1.0, 0.0)),
+        dict(kind="wall", axis=2, plane=2, law="nd", W=0.2, dir="normal")]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_forces_and_energy_fp64(ora, name):
+    c = dict(CASES[name])
+    say(f"[forces f64] {name} {c['shape']}")
+    p, lat = pair(ora, **c)
+    q = synth.random_field(11, p.N).reshape(p.field_shape)
+    F_ora = p.forces(q)
+    (E_ora, t_ora) = p.energy(q, terms=True)
+    qd = to_dev(q, torch.float64)
+    F = lat.compute_forces(qd)
+    e = lat.energy(qd)
+    torch.cuda.synchronize()
+    F = F.cpu().numpy()
+    scale = np.abs(F_ora).max()
+    assert np.abs(F - F_ora).max() <= 1e-12 * scale
+    assert abs(e["total"] - E_ora) <= 1e-12 * max(1.0, abs(E_ora))
+    for k, key in enumerate(("bulk", "elastic", "anchoring")):
+        assert abs(e[key] - t_ora[k]) <= 1e-12 * max(1.0, abs(t_ora[k]))
+    assert e["n_sim"] == p.n_sim
+
+
+@pytest.mark.parametrize("name", ["bulk32_L1", "ragged_periodic_L23", "colloid_slab24_L23",
+                                  "patterned_records_L23"])
+def test_forces_and_energy_fp32(ora, name):
+    c = dict(CASES[name])
+    say(f"[forces f32] {name} {c['shape']}")
+    p, lat = pair(ora, prec="f32", **c)
+    q32 = synth.random_field(12, p.N).reshape(p.field_shape).astype(np.float32)
+    q64 = q32.astype(np.float64)
+    F_ora = p.forces(q64)
+    E_ora = p.energy(q64)
+    qd = to_dev(q32, torch.float32)
+    F = lat.compute_forces(qd).cpu().numpy().astype(np.float64)
+    e = lat.energy(qd)
+    assert np.abs(F - F_ora).max() <= 1e-5 * np.abs(F_ora).max()
+    # the energy of an FP32 state is summed in FP64 from the exact float values
+    assert abs(e["total"] - E_ora) <= 1e-12 * max(1.0, abs(E_ora))
+
+
+def test_uniaxial_initial_state_is_bitwise(ora):
+    cfg = synth.colloid_slab(20, seed=3)
+    say("[init] colloid_slab20")
+    p, lat = pair(ora, cfg["shape"], L2=1.16, L3=1.16, objects=cfg["objects"])
+    dirs = synth.random_directors(3, p.N)
+    q_ora = p.uniaxial(dirs)
+    q = lat.set_uniaxial(to_dev(dirs, torch.float64), lat.empty())
+    assert np.array_equal(q.cpu().numpy(), q_ora)
+    lat32 = lqfire.Lattice(cfg["shape"], prec="f32", L2=1.16, L3=1.16)
+    lat32.set_boundaries(cfg["objects"])
+    q32 = lat32.set_uniaxial(to_dev(dirs, torch.float64), lat32.empty())
+    assert np.array_equal(q32.cpu().numpy(), q_ora.astype(np.float32))
+
+
+def _fire_trajectory(ora, p, lat, q0, steps, every, tol):
+    prm_o = ora.fire_params(force_tol=0.0, max_steps=10 ** 6)
+    st, qo, vo, Fo = p.fire_init(prm_o, q0)
+    q = to_dev(q0, torch.float64)
+    v, F = lat.empty(), lat.empty()
+    lat.fire_init(lqfire.make_fire_params(force_tol=0.0, max_steps=10 ** 6), q, v, F)
+    worst = 0.0
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        _, tr = p.fire_steps(prm_o, st, qo, vo, Fo, k, trace=True)
+        rep = lat.fire_step(k)
+        done += k
+        Fg = F.cpu().numpy()
+        err = np.abs(Fg - Fo).max() / np.abs(Fo).max()
+        worst = max(worst, err)
+        assert err <= tol, f"step {done}: force error {err:.3e}"
+        assert rep.step == st.step and rep.n_pos == st.n_pos and rep.restarts == st.restarts
+        assert rep.dt == pytest.approx(st.dt, rel=1e-15) and rep.alpha == pytest.approx(st.alpha, rel=1e-15)
+        assert abs(rep.P - st.P) <= 1e-9 * abs(st.P) + 1e-300
+    return worst, qo, q
+
+
+def test_fire_trajectory_bulk32(ora):
+    """32^3 periodic bulk box from a random director field (seed 0): the
+    force field agrees to 1e-10 at every one of the first 200 steps."""
+    cfg = synth.bulk32()
+    say("[fire] bulk32 200 steps")
+    p, lat = pair(ora, cfg["shape"])
+    q0 = p.uniaxial(synth.random_directors(0, p.N))
+    worst, qo, q = _fire_trajectory(ora, p, lat, q0, 200, 1, 1e-10)
+    say(f"  worst per-step relative force error {worst:.2e}")
+
+
+def test_fire_trajectory_walls_colloid_L23(ora):
+    cfg = synth.colloid_slab(16, seed=5)
+    cfg["objects"][2]["radius"] = 3.5
+    say("[fire] colloid_slab16 L23 150 steps")
+    p, lat = pair(ora, cfg["shape"], L2=1.16, L3=1.16, objects=cfg["objects"])
+    q0 = p.uniaxial(synth.random_directors(5, p.N))
+    _fire_trajectory(ora, p, lat, q0, 150, 10, 1e-10)
+
+
+def test_fire_steps_resume_bitwise():
+    """fire_step(30) + fire_step(20) equals fire_step(50) bit for bit, and so
+    does re-binding with the saved controller (lq_fire_init with resume)."""
+    say("[fire] resume")
+    cfg = synth.colloid_slab(16, seed=6)
+    cfg["objects"][2]["radius"] = 3.0
+    runs = []
+    for split in ([50], [30, 20], "resume"):
+        lat = lqfire.lattice_from_config(cfg)
+        dirs = to_dev(synth.random_directors(6, lat.N), torch.float64)
+        q = lat.set_uniaxial(dirs, lat.empty())
+        v, F = lat.empty(), lat.empty()
+        prm = lqfire.make_fire_params(force_tol=0.0, max_steps=10 ** 6)
+        lat.fire_init(prm, q, v, F)
+        if split == "resume":
+            rep = lat.fire_step(30)
+            q2, v2, F2 = q.clone(), v.clone(), lat.empty()
+            lat2 = lqfire.lattice_from_config(cfg)
+            lat2.fire_init(prm, q2, v2, F2, resume=rep)
+            assert torch.equal(F2, F)
+            lat2.fire_step(20)
+            q, v, F = q2, v2, F2
+        else:
+            for n in split:
+                lat.fire_step(n)
+        runs.append((q.cpu(), v.cpu(), F.cpu()))
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("anchor_dir", [(1.0, 0.0, 0.0), "normal"])
+def test_minimize_reaches_exact_wall_minimum(ora, anchor_dir):
+    """Walls preferring one director: the minimum is Q0 everywhere and
+    E = N_sim f0 (Eq. f0)."""
+    say(f"[minimize] walls {anchor_dir}")
+    objs = [dict(kind="wall", axis=2, plane=0, law="nd", W=0.5, dir=anchor_dir),
+            dict(kind="wall", axis=2, plane=13, law="nd", W=0.5, dir=anchor_dir)]
+    lat = lqfire.Lattice((24, 20, 14), L2=1.16, L3=1.16)
+    lat.set_boundaries(objs)
+    q = lat.set_uniaxial(to_dev(synth.random_directors(8, lat.N), torch.float64), lat.empty())
+    rep, q, v, F = lat.minimize(lqfire.make_fire_params(force_tol=1e-10, max_steps=50000), q)
+    assert rep.status == lqfire.CONVERGED, rep.as_dict()
+    s0 = lat.S0
+    f0 = 0.75 * A * s0 ** 2 + 0.25 * B * s0 ** 3 + 9.0 / 16.0 * C * s0 ** 4
+    e = lat.energy(q)
+    assert abs(e["total"] - e["n_sim"] * f0) <= 1e-9 * abs(e["n_sim"] * f0)
+    n = np.array([1.0, 0.0, 0.0]) if anchor_dir != "normal" else np.array([0.0, 0.0, 1.0])
+    Q0 = 1.5 * s0 * (np.outer(n, n) - np.eye(3) / 3)
+    q0 = np.array([Q0[0, 0], Q0[0, 1], Q0[0, 2], Q0[1, 1], Q0[1, 2]])
+    qa = q.cpu().numpy()
+    sim = np.ones(qa.shape[1:], bool)
+    sim[[0, 13]] = False
+    assert np.abs(qa[:, sim] - q0[:, None]).max() < 1e-6
+
+
+def test_minimize_colloid_matches_oracle_minimum(ora):
+    """A 12^3 slab with a colloid minimized to max|F| < 1e-9 on both sides
+    along the same trajectory: energies to 1e-6, max |dQ| < 1e-5."""
+    say("[minimize] colloid 12^3 vs oracle")
+    cfg = synth.colloid_slab(12, seed=7)
+    cfg["objects"][2]["radius"] = 2.5
+    p, lat = pair(ora, cfg["shape"], L2=1.16, L3=1.16, objects=cfg["objects"])
+    q0 = p.uniaxial(synth.random_directors(7, p.N))
+    st, qo, vo, Fo = p.minimize(ora.fire_params(force_tol=1e-9, max_steps=50000), q0)
+    rep, q, v, F = lat.minimize(lqfire.make_fire_params(force_tol=1e-9, max_steps=50000),
+                                to_dev(q0, torch.float64))
+    assert st.status == ora.CONVERGED and rep.status == lqfire.CONVERGED
+    E_o = p.energy(qo)
+    e = lat.energy(q)["total"]
+    assert abs(e - E_o) <= 1e-6 * abs(E_o)
+    assert np.abs(q.cpu().numpy() - qo).max() < 1e-5
+    say(f"  steps gpu {rep.step} oracle {st.step}; |dE|/E {abs(e - E_o) / abs(E_o):.2e}")
+
+
+def test_fp32_then_fp64_polish_reaches_wall_minimum():
+    """Precision form: FP32 FIRE to 1e-5, then an FP64 polish from the FP32
+    state reaches the exact minimum of the wall box."""
+    say("[fp32+polish] walls")
+    objs = [dict(kind="wall", axis=2, plane=0, law="nd", W=0.5, dir=(1.0, 0.0, 0.0)),
+            dict(kind="wall", axis=2, plane=13, law="nd", W=0.5, dir=(1.0, 0.0, 0.0))]
+    lat32 = lqfire.Lattice((24, 20, 14), prec="f32", L2=1.16, L3=1.16)
+    lat32.set_boundaries(objs)
+    q32 = lat32.set_uniaxial(to_dev(synth.random_directors(8, lat32.N), torch.float64), lat32.empty())
+    rep32, q32, _, _ = lat32.minimize(lqfire.make_fire_params(force_tol=1e-5, max_steps=50000), q32)
+    assert rep32.status == lqfire.CONVERGED
+    lat64 = lqfire.Lattice((24, 20, 14), prec="f64", L2=1.16, L3=1.16)
+    lat64.set_boundaries(objs)
+    q = q32.double().contiguous()
+    rep, q, _, _ = lat64.minimize(lqfire.make_fire_params(force_tol=1e-10, max_steps=50000), q)
+    assert rep.status == lqfire.CONVERGED
+    s0 = lat64.S0
+    f0 = 0.75 * A * s0 ** 2 + 0.25 * B * s0 ** 3 + 9.0 / 16.0 * C * s0 ** 4
+    e = lat64.energy(q)
+    assert abs(e["total"] - e["n_sim"] * f0) <= 1e-9 * abs(e["n_sim"] * f0)
+    say(f"  fp32 steps {rep32.step}, fp64 polish steps {rep.step}")
+
+
+def test_error_paths():
+    say("[errors]")
+    lat = lqfire.Lattice((8, 8, 8))
+    with pytest.raises(lqfire.LQError) as e:
+        lat.fire_step(1)
+    assert e.value.code == lqfire.LQ_ESTATE
+    q, v, F = lat.zeros(), lat.zeros(), lat.zeros()
+    import ctypes as Cc
+    host = np.zeros(5 * lat.N)
+    rc = lqfire.lib().lq_compute_forces(lat.h, Cc.c_void_p(host.ctypes.data), Cc.c_void_p(F.data_ptr()))
+    assert rc == lqfire.LQ_EINVAL
+    ws = torch.empty(64, dtype=torch.uint8, device="cuda")
+    prm = lqfire.make_fire_params()
+    rc = lqfire.lib().lq_fire_init(lat.h, Cc.byref(prm), Cc.c_void_p(q.data_ptr()), Cc.c_void_p(v.data_ptr()),
+                                   Cc.c_void_p(F.data_ptr()), Cc.c_void_p(ws.data_ptr()), 64, None)
+    assert rc == lqfire.LQ_ENOMEM
+    qn = lat.zeros()
+    qn[0, 3, 3, 3] = float("nan")
+    with pytest.raises(lqfire.LQError) as e:
+        lat.minimize(prm, qn)
+    assert e.value.code == lqfire.LQ_ENONFINITE
+    # the isotropic state is stationary: converged before the first step
+    rep, _, _, _ = lat.minimize(lqfire.make_fire_params(force_tol=1e-12), lat.zeros())
+    assert rep.status == lqfire.CONVERGED and rep.step == 0
+    rep, _, _, _ = lat.minimize(lqfire.make_fire_params(max_steps=0), lat.empty().copy_(
+        to_dev(synth.random_field(1, lat.N).reshape(lat.field_shape), torch.float64)))
+    assert rep.status == lqfire.MAX_STEPS and rep.step == 0
+    with pytest.raises(ValueError):
+        lat.compute_forces(q.cpu())
+
+
+def _sampled_sites(p, rng, n):
+    sites = rng.choice(p.N, size=n, replace=False)
+    bnd = np.nonzero(p.types == 1)[0]
+    if len(bnd):
+        sites = np.concatenate([sites, rng.choice(bnd, size=min(n, len(bnd)), replace=False)])
+    return np.unique(sites)
+
+
+@pytest.mark.parametrize("which", ["colloid_slab128_f64", "multi_colloid256_f32"])
+def test_full_size_forces_sampled(ora, which):
+    """Full workload sizes: GPU forces at sampled sites (random plus boundary)
+    against the oracle evaluated at those sites only."""
+    cfg = synth.colloid_slab(128) if which.startswith("colloid") else synth.multi_colloid(256)
+    prec = "f64" if which.endswith("f64") else "f32"
+    say(f"[full size] {which}")
+    p = ora.Problem(cfg["shape"], cfg["periodic"], L1=cfg["L1"], L2=cfg["L2"], L3=cfg["L3"],
+                    objects=cfg["objects"])
+    lat = lqfire.lattice_from_config(cfg, prec=prec)
+    q = synth.random_field(21, p.N).reshape(p.field_shape)
+    if prec == "f32":
+        q = q.astype(np.float32).astype(np.float64)
+    Fd = lat.compute_forces(to_dev(q, lat.dtype)).cpu().numpy().reshape(5, -1)
+    sites = _sampled_sites(p, np.random.default_rng(0), 1500)
+    Fo = p.forces_at(q, sites)
+    Fg = Fd[:, sites].T.astype(np.float64)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert np.abs(Fg - Fo).max() <= tol * np.abs(Fo).max()
+
+
+def test_full_size_fused_step_consistency(ora):
+    """256^3 with 8 colloids, FP32, in the launch configuration the benchmark
+    times: after one fused FIRE step from rest, F equals compute_forces(q)
+    bit for bit, and at sampled sites q1 - q0 = dt0^2/2 F_oracle(q0)."""
+    cfg = synth.multi_colloid(256)
+    say("[full size] fused step 256^3 f32")
+    p = ora.Problem(cfg["shape"], cfg["periodic"], L1=cfg["L1"], objects=cfg["objects"])
+    lat = lqfire.lattice_from_config(cfg, prec="f32")
+    dirs = synth.random_directors(cfg["dir_seed"], p.N)
+    q0h = p.uniaxial(dirs).astype(np.float32)
+    q = to_dev(q0h, torch.float32)
+    v, F = lat.empty(), lat.empty()
+    lat.fire_init(lqfire.fire_params_from_config(cfg), q, v, F)
+    rep = lat.fire_step(1)
+    assert rep.step == 1
+    F_again = lat.compute_forces(q)
+    assert torch.equal(F_again, F)
+    sites = _sampled_sites(p, np.random.default_rng(1), 800)
+    F0 = p.forces_at(q0h.astype(np.float64), sites)
+    dq = (q.cpu().numpy().reshape(5, -1)[:, sites].astype(np.float64)
+          - q0h.reshape(5, -1)[:, sites].astype(np.float64)).T
+    dt0 = cfg["fire"]["dt0"]
+    ref = 0.5 * dt0 * dt0 * F0
+    assert np.abs(dq - ref).max() <= 2e-7 * np.abs(q0h).max() + 1e-5 * np.abs(ref).max()
