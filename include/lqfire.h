@@ -52,7 +52,9 @@ typedef struct lq_lattice lq_lattice;
 
 /* Lattice and constants (sec. III.B: everything in units of |A| and dx). */
 typedef struct {
-    int64_t n[3];        /* nx, ny, nz >= 1; >= 3 on a periodic axis */
+    int64_t n[3];        /* nx, ny, nz >= 1; >= 3 on a periodic axis; one field of
+                            5 N values must fit in 2^32 bytes (N < 107374182 for
+                            LQ_F64, N < 214748364 for LQ_F32) */
     int32_t periodic[3]; /* 1 = periodic axis, 0 = open (neighbours off the edge are absent) */
     int32_t prec;        /* LQ_F64 or LQ_F32 */
     double A, B, C;      /* bulk coefficients, Eq. (fphase); C > 0 */

@@ -69,6 +69,8 @@ def lib():
             build(force=False)
         L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)
+        L.ora_threads.restype = C.c_int
+        L.ora_threads.argtypes = []
         L.ora_S0.restype = C.c_double
         L.ora_S0.argtypes = [C.c_double, C.c_double, C.c_double]
         L.ora_energy.restype = C.c_double
@@ -98,6 +100,11 @@ def lib():
 def _dp(a):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use (OpenMP)."""
+    return int(lib().ora_threads())
 
 
 def S0(A, B, C_):

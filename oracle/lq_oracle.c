@@ -22,8 +22,7 @@
  *     (sec. III.B, the paragraph on explicit differentiation);
  *   - FIRE, Algorithm 1 (after Bitzek et al., PRL 97, 170201 (2006)).
  *
- * Readings of points the paper leaves open are listed in the design doc; the ones
- * that shape this code are repeated where they act.
+ * Readings of points the paper leaves open are stated where they act.
  *
  * Layout: every per-site field is SoA, component c of site s at [c*N + s],
  * s = x + nx*(y + ny*z).  Site type: 0 bulk, 1 boundary, 2 inside an object.
@@ -44,6 +43,20 @@ typedef struct {
     const double *pair_W;  /* Nobili-Durand strength used for the pair */
     const double *pair_Q0; /* [n_pairs][5] preferred tensor, q components */
 } ora_problem;
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* number of threads the parallel loops use */
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ---- Eq. (S0def): the nematic minimum of the uniaxial bulk density ---- */
 double ora_S0(double A, double B, double C)

@@ -95,6 +95,11 @@ static int check_params(const lq_params* p, std::string& err) {
         err = "prec must be LQ_F64 or LQ_F32";
         return LQ_EINVAL;
     }
+    // the kernels address one field (5 N values) with 32-bit byte offsets
+    if (5.0 * N * (p->prec == LQ_F64 ? 8.0 : 4.0) > 4294967295.0) {
+        err = "a field of 5 N values exceeds 2^32 bytes (FP64: N < 107374182, FP32: N < 214748364)";
+        return LQ_EINVAL;
+    }
     const double c[] = {p->A, p->B, p->C, p->L1, p->L2, p->L3, p->L4, p->L6};
     for (double x : c)
         if (!std::isfinite(x)) {

@@ -28,8 +28,9 @@
 // never waits between steps.
 //
 // Layout: SoA fields [5][nz][ny][nx].  A block owns a TX x TY column tile and
-// marches ZC planes along z, keeping four planes of updated q (with halo) in
-// LDS so that one barrier per plane suffices.
+// marches zc planes along z, keeping the drifted q of four planes with their
+// halo in LDS: the force of plane f reads planes f-1, f, f+1 while plane f+1
+// is being written, so that one barrier per plane suffices.
 #include <hip/hip_runtime.h>
 
 #include "lq_internal.h"
@@ -38,11 +39,34 @@ namespace lq {
 
 constexpr int PX = TX + 2;
 constexpr int PY = TY + 2;
-constexpr int NSLOT = 4;
-constexpr int RING = 2 * PX + 2 * (PY - 2);
 
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+
+// Raw buffer access to one field (5 components, 5 N elements): the resource
+// covers exactly the field, so an offset past its end reads 0 and drops the
+// store; the component offset c N sizeof(T) goes in the scalar offset and the
+// site offset in one 32-bit vector register.  A field must fit in 2^32 bytes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    }
+}
+template <typename T>
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v) {
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+    } else {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+    }
+}
 
 __device__ __forceinline__ int wrapc(int g, int n, int per) {
     if (g >= 0 && g < n) return g;
@@ -91,25 +115,26 @@ __device__ __forceinline__ void pT(const T G[3][3], T g[5]) {
     g[4] = G[1][2] + G[2][1];
 }
 
-// d(bulk)/dq: P^T (A Q + B Q^2 + C tr(Q^2) Q)
+// d(bulk)/dq = P^T (A Q + B Q^2 + C tr(Q^2) Q), written out in the five
+// components: P^T Q = M q and P^T S = (Sxx - Szz, 2 Sxy, 2 Sxz, Syy - Szz,
+// 2 Syz) for the symmetric S = Q^2.
 template <typename T>
 __device__ __forceinline__ void bulk_grad(const T q[5], T A, T B, T C, T g[5]) {
-    T Q[3][3];
-    full_of(q, Q);
-    T t2 = T(0);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) t2 = fma_t(Q[i][j], Q[i][j], t2);
-    T G[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            T qq = Q[a][0] * Q[0][b] + Q[a][1] * Q[1][b] + Q[a][2] * Q[2][b];
-            G[a][b] = (A + C * t2) * Q[a][b] + B * qq;
-        }
-    pT(G, g);
+    const T zz = -q[0] - q[3];
+    const T s01 = q[1] * q[1], s02 = q[2] * q[2], s04 = q[4] * q[4];
+    const T t2 = q[0] * q[0] + q[3] * q[3] + zz * zz + T(2) * (s01 + s02 + s04);
+    const T Sxx = q[0] * q[0] + s01 + s02;
+    const T Syy = s01 + q[3] * q[3] + s04;
+    const T Szz = s02 + s04 + zz * zz;
+    const T Sxy = q[0] * q[1] + q[1] * q[3] + q[2] * q[4];
+    const T Sxz = q[0] * q[2] + q[1] * q[4] + q[2] * zz;
+    const T Syz = q[1] * q[2] + q[3] * q[4] + q[4] * zz;
+    const T a = A + C * t2;
+    g[0] = a * (T(2) * q[0] + q[3]) + B * (Sxx - Szz);
+    g[1] = T(2) * (a * q[1] + B * Sxy);
+    g[2] = T(2) * (a * q[2] + B * Sxz);
+    g[3] = a * (q[0] + T(2) * q[3]) + B * (Syy - Szz);
+    g[4] = T(2) * (a * q[4] + B * Syz);
 }
 
 // The bond (L1) metric: sum_ij dQ_ij^2 = d^T M d; returns M d.
@@ -161,20 +186,22 @@ __device__ __forceinline__ void cross_h(int j, const T Ck[3][5], T L2, T L3, T h
 }
 
 // ---------------------------------------------------------------------------
-// Stencil over the LDS planes.  Offsets (dx, dy, dz) in {-1, 0, 1}; the
-// centre is (tx+1, ty+1) of the middle slot.
-template <typename T>
-struct Planes {
+// Stencil view used by the force: offsets (dx, dy, dz) in {-1, 0, 1} around
+// the centre, read from the LDS slots of the planes below, at and above the
+// centre.  BULK: every site of the padded tile is simulated with all six
+// neighbours, so masks are compile-time constants.
+template <typename T, bool L23, bool BULK>
+struct Stencil {
     T (*q)[5][PY][PX];
     uint8_t (*m)[PY][PX];
-    int s[3];  // slots of planes z-1, z, z+1
+    int s[3];  // LDS slots of the planes below, at and above the centre
     int cx, cy;
-    bool bulk;
     __device__ __forceinline__ T at(int dx, int dy, int dz, int c) const {
         return q[s[dz + 1]][c][cy + dy][cx + dx];
     }
     __device__ __forceinline__ uint32_t mask(int dx, int dy, int dz) const {
-        return bulk ? (uint32_t)M_FULL : (uint32_t)m[s[dz + 1]][cy + dy][cx + dx];
+        if (BULK) return (uint32_t)M_FULL;
+        return (uint32_t)m[s[dz + 1]][cy + dy][cx + dx];
     }
     __device__ __forceinline__ void load5(int dx, int dy, int dz, T o[5]) const {
 #pragma unroll
@@ -189,9 +216,9 @@ __device__ __forceinline__ void unit(int k, int s, int& dx, int& dy, int& dz) {
 }
 
 // mean differences C_k (k != skip) at offset o of the stencil
-template <typename T>
-__device__ __forceinline__ void mean_diffs(const Planes<T>& P, int ox, int oy, int oz, int skip,
-                                           uint32_t m, T Ck[3][5]) {
+template <typename T, bool L23, bool BULK>
+__device__ __forceinline__ void mean_diffs(const Stencil<T, L23, BULK>& P, int ox, int oy, int oz,
+                                           int skip, uint32_t m, T Ck[3][5]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         if (k == skip) {
@@ -214,41 +241,55 @@ __device__ __forceinline__ void mean_diffs(const Planes<T>& P, int ox, int oy, i
 }
 
 // -dE/dq at the stencil centre (a simulated site with mask m0).
-template <typename T, bool L23>
-__device__ __forceinline__ void site_force(const Planes<T>& P, uint32_t m0, const LatDev& L,
-                                           int64_t site, T F[5]) {
+template <typename T, bool L23, bool BULK>
+__device__ __forceinline__ void site_force(const Stencil<T, L23, BULK>& P, uint32_t m0,
+                                           const LatDev& L, int site, T F[5]) {
     const T A = T(L.A), B = T(L.B), C = T(L.C), L1 = T(L.L1);
     T q0[5];
     P.load5(0, 0, 0, q0);
     T g[5];
     bulk_grad(q0, A, B, C, g);
-    // bond sums: L1 and the same-axis part of L2/L3
+    if (BULK && !L23) {
+        // every bond has weight 1: the L1 term is -L1 M (sum of neighbours - 6 q)
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int s = -1; s <= 1; s += 2) {
-            if (!has_nb(m0, k, s)) continue;
-            int dx, dy, dz;
-            unit(k, s, dx, dy, dz);
-            uint32_t mn = P.mask(dx, dy, dz);
-            T w = (n_choices(m0, k) == 2 ? T(0.5) : T(1)) + (n_choices(mn, k) == 2 ? T(0.5) : T(1));
-            T d[5], o[5];
-#pragma unroll
-            for (int c = 0; c < 5; ++c) d[c] = q0[c] - P.at(dx, dy, dz, c);
-            metric(d, o);
-            T wl = w * L1;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) g[c] = fma_t(wl, o[c], g[c]);
-            if (L23) {
-                column_metric(k, d, o);
-                T wl23 = w * (T(L.L2) + T(L.L3));
-#pragma unroll
-                for (int c = 0; c < 5; ++c) g[c] = fma_t(wl23, o[c], g[c]);
-            }
+        for (int c = 0; c < 5; ++c) {
+            T lap = ((P.at(1, 0, 0, c) + P.at(-1, 0, 0, c)) + (P.at(0, 1, 0, c) + P.at(0, -1, 0, c)))
+                    + (P.at(0, 0, 1, c) + P.at(0, 0, -1, c));
+            F[c] = fma_t(T(-6), q0[c], lap);
         }
+        T o[5];
+        metric(F, o);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) g[c] = fma_t(-L1, o[c], g[c]);
+    } else {
+        // bond sums: L1 and the same-axis part of L2/L3
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int s = -1; s <= 1; s += 2) {
+                if (!has_nb(m0, k, s)) continue;
+                int dx, dy, dz;
+                unit(k, s, dx, dy, dz);
+                uint32_t mn = P.mask(dx, dy, dz);
+                T w = (n_choices(m0, k) == 2 ? T(0.5) : T(1)) + (n_choices(mn, k) == 2 ? T(0.5) : T(1));
+                T d[5], o[5];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) d[c] = q0[c] - P.at(dx, dy, dz, c);
+                metric(d, o);
+                T wl = w * L1;
+#pragma unroll
+                for (int c = 0; c < 5; ++c) g[c] = fma_t(wl, o[c], g[c]);
+                if (L23) {
+                    column_metric(k, d, o);
+                    T wl23 = w * (T(L.L2) + T(L.L3));
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) g[c] = fma_t(wl23, o[c], g[c]);
+                }
+            }
+    }
     if (L23) {
         const T L2 = T(L.L2), L3 = T(L.L3);
-        // cross-axis part: sum over sites x whose C_j uses Q(centre)
+        // cross-axis part: every site x whose mean difference C_j contains Q(centre)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
 #pragma unroll
@@ -278,12 +319,12 @@ __device__ __forceinline__ void site_force(const Planes<T>& P, uint32_t m0, cons
             }
         }
     }
-    if (m0 & M_ANCH) {
+    if (!BULK && (m0 & M_ANCH)) {
         // binary search of the site in the sorted anchored list
         int lo = 0, hi = L.n_anch - 1, at = -1;
         while (lo <= hi) {
             int mid = (lo + hi) >> 1;
-            int64_t sv = L.anch_site[mid];
+            int sv = L.anch_site[mid];
             if (sv == site) { at = mid; break; }
             if (sv < site) lo = mid + 1; else hi = mid - 1;
         }
@@ -418,12 +459,187 @@ __device__ void grid_finish(double r[4], double* partials, FireDev* st, int nblo
 // ---------------------------------------------------------------------------
 // The z-marching kernel.  STEP = false: F = force(q) only.  STEP = true: one
 // fused FIRE step between the two buffers of b.
+//
+// A block owns a TX x TY column tile and the planes z0 .. z0+zc-1.  Plane i
+// of the march (global z = z0 - 1 + i, i = 0 .. zc+1) is loaded into
+// registers (the block's own sites, plus the one-site ring around the tile
+// spread over all threads one (site, component) pair at a time), then drifted
+// (steering, first half kick, q += dt v) into an LDS slot.  Loads run one
+// plane ahead of the drift, so the loads of plane i+1 are in flight while the
+// force of plane i-1 is evaluated.
+constexpr int RING = 2 * PX + 2 * (PY - 2);
+constexpr int RING_ITEMS = 5 * RING;
+constexpr int ITEMS_PER_THREAD = (RING_ITEMS + NTHREADS - 1) / NTHREADS;
+
+__device__ __forceinline__ void ring_pos(int r, int& px, int& py) {
+    if (r < PX) { px = r; py = 0; }
+    else if (r < 2 * PX) { px = r - PX; py = PY - 1; }
+    else if (r < 2 * PX + PY - 2) { px = 0; py = r - 2 * PX + 1; }
+    else { px = PX - 1; py = r - 2 * PX - (PY - 2) + 1; }
+}
+
+template <typename T, bool L23, bool STEP, bool BULK>
+__device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_in,
+                                      const T* __restrict__ v_in, const T* __restrict__ F_in,
+                                      T* __restrict__ q_out, T* __restrict__ v_out,
+                                      T* __restrict__ F_out, T cv, T cF, T dt, T hdt, int x0, int y0,
+                                      int z0, int zc, T (*sq)[5][PY][PX], uint8_t (*sm)[PY][PX],
+                                      double red[4]) {
+    constexpr int NS = 4;
+    const int64_t N = L.N;
+    const int nxy = L.nx * L.ny;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool own_xy = gx < L.nx && gy < L.ny;
+    int sxy_own;
+    {
+        const int wx = wrapc(gx, L.nx, L.per[0]), wy = wrapc(gy, L.ny, L.per[1]);
+        sxy_own = (wx >= 0 && wy >= 0) ? wx + L.nx * wy : -1;
+    }
+    // ring items of this thread
+    int it_c[ITEMS_PER_THREAD], it_px[ITEMS_PER_THREAD], it_py[ITEMS_PER_THREAD], it_sxy[ITEMS_PER_THREAD];
+#pragma unroll
+    for (int j = 0; j < ITEMS_PER_THREAD; ++j) {
+        const int k = threadIdx.x + j * NTHREADS;
+        it_c[j] = -1; it_px[j] = 0; it_py[j] = 0; it_sxy[j] = -1;
+        if (k < RING_ITEMS) {
+            it_c[j] = k / RING;
+            ring_pos(k % RING, it_px[j], it_py[j]);
+            const int wx = wrapc(x0 - 1 + it_px[j], L.nx, L.per[0]);
+            const int wy = wrapc(y0 - 1 + it_py[j], L.ny, L.per[1]);
+            it_sxy[j] = (wx >= 0 && wy >= 0) ? wx + L.nx * wy : -1;
+        }
+    }
+    // raw data of the next plane to drift
+    T rq[5], rv[5], rf[5];
+    T iq[ITEMS_PER_THREAD], iv[ITEMS_PER_THREAD], iF[ITEMS_PER_THREAD];
+    uint32_t rm = 0, im[ITEMS_PER_THREAD];
+
+    const uint32_t cs = (uint32_t)N * (uint32_t)sizeof(T);  // bytes per component
+    const uint32_t fb = 5u * cs;                               // bytes per field
+    const __amdgpu_buffer_rsrc_t rq_in = field_rsrc(q_in, fb);
+    const __amdgpu_buffer_rsrc_t rv_in = field_rsrc(STEP ? v_in : q_in, fb);
+    const __amdgpu_buffer_rsrc_t rF_in = field_rsrc(STEP ? F_in : q_in, fb);
+    const __amdgpu_buffer_rsrc_t rq_out = field_rsrc(STEP ? q_out : F_out, fb);
+    const __amdgpu_buffer_rsrc_t rv_out = field_rsrc(STEP ? v_out : F_out, fb);
+    const __amdgpu_buffer_rsrc_t rF_out = field_rsrc(F_out, fb);
+    auto load = [&](int i) {
+        const int wz = wrapc(z0 - 1 + i, L.nz, L.per[2]);
+        const int s = (sxy_own >= 0 && wz >= 0) ? sxy_own + nxy * wz : -1;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) { rq[c] = T(0); rv[c] = T(0); rf[c] = T(0); }
+        rm = 0;
+        if (s >= 0) {
+            const uint32_t off = (uint32_t)s * (uint32_t)sizeof(T);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                rq[c] = bld<T>(rq_in, off, c * cs);
+                if (STEP) { rv[c] = bld<T>(rv_in, off, c * cs); rf[c] = bld<T>(rF_in, off, c * cs); }
+            }
+            if (!BULK) rm = L.mask[s];
+        }
+#pragma unroll
+        for (int j = 0; j < ITEMS_PER_THREAD; ++j) {
+            iq[j] = T(0); iv[j] = T(0); iF[j] = T(0); im[j] = 0;
+            const int t = (it_sxy[j] >= 0 && wz >= 0) ? it_sxy[j] + nxy * wz : -1;
+            if (t >= 0) {
+                const uint32_t off = ((uint32_t)it_c[j] * (uint32_t)N + (uint32_t)t) * (uint32_t)sizeof(T);
+                iq[j] = bld<T>(rq_in, off, 0u);
+                if (STEP) { iv[j] = bld<T>(rv_in, off, 0u); iF[j] = bld<T>(rF_in, off, 0u); }
+                if (!BULK && it_c[j] == 0) im[j] = L.mask[t];
+            }
+        }
+    };
+    // drift the registers into LDS slot; returns the own site's q' and v1
+    auto drift = [&](int slot, T qn[5], T v1[5], uint32_t& m) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            if (STEP) {
+                const T vm = fma_t(cv, rv[c], cF * rf[c]);
+                v1[c] = fma_t(hdt, rf[c], vm);
+                qn[c] = fma_t(dt, v1[c], rq[c]);
+            } else {
+                qn[c] = rq[c];
+                v1[c] = T(0);
+            }
+            sq[slot][c][ty + 1][tx + 1] = qn[c];
+        }
+        m = BULK ? (uint32_t)M_FULL : rm;
+        if (!BULK) sm[slot][ty + 1][tx + 1] = (uint8_t)rm;
+#pragma unroll
+        for (int j = 0; j < ITEMS_PER_THREAD; ++j) {
+            if (it_c[j] < 0) continue;
+            T x = iq[j];
+            if (STEP) {
+                const T vm = fma_t(cv, iv[j], cF * iF[j]);
+                x = fma_t(dt, fma_t(hdt, iF[j], vm), x);
+            }
+            sq[slot][it_c[j]][it_py[j]][it_px[j]] = x;
+            if (!BULK && it_c[j] == 0) sm[slot][it_py[j]][it_px[j]] = (uint8_t)im[j];
+        }
+    };
+    auto slot_of = [](int i) { return i & (NS - 1); };
+
+    T v1_cur[5], v1_next[5], q_unused[5], v1_unused[5];
+    uint32_t m_cur, m_next, m_unused;
+    load(0);
+    drift(slot_of(0), q_unused, v1_unused, m_unused);
+    load(1);
+    drift(slot_of(1), q_unused, v1_cur, m_cur);
+    load(2);
+    for (int f = 1; f <= zc; ++f) {
+        drift(slot_of(f + 1), q_unused, v1_next, m_next);
+        if (f + 2 <= zc + 1) load(f + 2);
+        __syncthreads();
+        if (own_xy) {
+            const int s = gx + L.nx * gy + nxy * (z0 + f - 1);
+            const uint32_t off = (uint32_t)s * (uint32_t)sizeof(T);
+            if (m_cur & M_SIM) {
+                Stencil<T, L23, BULK> P;
+                P.q = sq; P.m = sm;
+                P.s[0] = slot_of(f - 1); P.s[1] = slot_of(f); P.s[2] = slot_of(f + 1);
+                P.cx = tx + 1; P.cy = ty + 1;
+                T F[5];
+                site_force<T, L23, BULK>(P, m_cur, L, s, F);
+                if (STEP) {
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) {
+                        const T v2 = fma_t(hdt, F[c], v1_cur[c]);
+                        bst<T>(rq_out, off, c * cs, P.at(0, 0, 0, c));
+                        bst<T>(rv_out, off, c * cs, v2);
+                        bst<T>(rF_out, off, c * cs, F[c]);
+                        const double fd = (double)F[c], vd = (double)v2;
+                        red[0] = fma(fd, vd, red[0]);
+                        red[1] = fma(fd, fd, red[1]);
+                        red[2] = fma(vd, vd, red[2]);
+                        red[3] = fmax(red[3], fabs(fd));
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) bst<T>(rF_out, off, c * cs, F[c]);
+                }
+            } else {
+                // sites inside objects carry no degrees of freedom
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    bst<T>(rF_out, off, c * cs, T(0));
+                    if (STEP) { bst<T>(rq_out, off, c * cs, T(0)); bst<T>(rv_out, off, c * cs, T(0)); }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) v1_cur[c] = v1_next[c];
+        m_cur = m_next;
+    }
+}
+
 template <typename T, bool L23, bool STEP>
 __global__ __launch_bounds__(NTHREADS) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
                                                     T* __restrict__ Fout, double* partials,
                                                     FireDev* st) {
-    __shared__ T sq[NSLOT][5][PY][PX];
-    __shared__ uint8_t sm[NSLOT][PY][PX];
+    constexpr int NS = 4;
+    __shared__ T sq[NS][5][PY][PX];
+    __shared__ uint8_t sm[NS][PY][PX];
     __shared__ double scratch[NTHREADS / 64][4];
     __shared__ int last_flag;
 
@@ -432,17 +648,11 @@ __global__ __launch_bounds__(NTHREADS) void k_march(LatDev L, Bufs<T> b, const T
     // keep neighbouring tiles on one XCD: dispatch is round-robin over 8 XCDs
     if ((nblocks & 7) == 0) bid = (bid & 7) * (nblocks >> 3) + (bid >> 3);
     const int bx = bid % L.ntx, by = (bid / L.ntx) % L.nty, bz = bid / (L.ntx * L.nty);
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * L.zc;
-    const bool bulk = L.tile_bulk[bid] != 0;
-    const int64_t N = L.N;
+    const int zc = min(L.zc, L.nz - z0);
 
-    const T* q_in;
-    const T* v_in = nullptr;
-    const T* F_in = nullptr;
-    T* q_out = nullptr;
-    T* v_out = nullptr;
-    T* F_out;
+    const T *q_in, *v_in = nullptr, *F_in = nullptr;
+    T *q_out = nullptr, *v_out = nullptr, *F_out;
     T cv = T(1), cF = T(0), dt = T(0), hdt = T(0);
     if (STEP) {
         if (st->done) return;
@@ -456,115 +666,13 @@ __global__ __launch_bounds__(NTHREADS) void k_march(LatDev L, Bufs<T> b, const T
         q_in = qin;
         F_out = Fout;
     }
-
-    const int gx_own = x0 + tx, gy_own = y0 + ty;
-    const bool own_xy = gx_own < L.nx && gy_own < L.ny;
-    const int wx_own = wrapc(gx_own, L.nx, L.per[0]);
-    const int wy_own = wrapc(gy_own, L.ny, L.per[1]);
-
     double red[4] = {0.0, 0.0, 0.0, 0.0};
-    T v1_prev[5], v1_cur[5];
-    uint32_t m_prev = 0, m_cur = 0;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) { v1_prev[c] = T(0); v1_cur[c] = T(0); }
-
-    const int zc = min(L.zc, L.nz - z0);
-    for (int i = 0; i <= zc + 1; ++i) {
-        const int slot = i & (NSLOT - 1);
-        const int wz = wrapc(z0 - 1 + i, L.nz, L.per[2]);
-        // rotate the per-thread pipeline: v1 of the plane that will get its force next
-#pragma unroll
-        for (int c = 0; c < 5; ++c) v1_prev[c] = v1_cur[c];
-        m_prev = m_cur;
-        // own position (interior of the padded plane), then the halo ring
-        for (int r = threadIdx.x; r < NTHREADS + RING; r += NTHREADS) {
-            int px, py, wx, wy;
-            if (r < NTHREADS) {
-                px = tx + 1; py = ty + 1; wx = wx_own; wy = wy_own;
-            } else {
-                int k = r - NTHREADS;
-                if (k < PX) { px = k; py = 0; }
-                else if (k < 2 * PX) { px = k - PX; py = PY - 1; }
-                else if (k < 2 * PX + PY - 2) { px = 0; py = k - 2 * PX + 1; }
-                else { px = PX - 1; py = k - 2 * PX - (PY - 2) + 1; }
-                wx = wrapc(x0 - 1 + px, L.nx, L.per[0]);
-                wy = wrapc(y0 - 1 + py, L.ny, L.per[1]);
-            }
-            uint32_t m = 0;
-            T qn[5] = {T(0), T(0), T(0), T(0), T(0)};
-            T v1[5] = {T(0), T(0), T(0), T(0), T(0)};
-            if (wx >= 0 && wy >= 0 && wz >= 0) {
-                const int64_t s = (int64_t)wx + (int64_t)L.nx * ((int64_t)wy + (int64_t)L.ny * wz);
-                m = bulk ? (uint32_t)M_FULL : (uint32_t)L.mask[s];
-                if (m & M_SIM) {
-                    if (STEP) {
-#pragma unroll
-                        for (int c = 0; c < 5; ++c) {
-                            T q = q_in[c * N + s], v = v_in[c * N + s], f = F_in[c * N + s];
-                            T vm = fma_t(cv, v, cF * f);
-                            v1[c] = fma_t(hdt, f, vm);
-                            qn[c] = fma_t(dt, v1[c], q);
-                        }
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < 5; ++c) qn[c] = q_in[c * N + s];
-                    }
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < 5; ++c) sq[slot][c][py][px] = qn[c];
-            sm[slot][py][px] = (uint8_t)m;
-            if (r < NTHREADS) {
-#pragma unroll
-                for (int c = 0; c < 5; ++c) v1_cur[c] = v1[c];
-                m_cur = m;
-            }
-        }
-        __syncthreads();
-        if (i < 2) continue;
-        // force at plane index i-1 (global z = z0 + i - 2)
-        const int zf = z0 + i - 2;
-        if (own_xy && (m_prev & M_SIM)) {
-            Planes<T> P;
-            P.q = sq; P.m = sm;
-            P.s[0] = (i - 2) & (NSLOT - 1);
-            P.s[1] = (i - 1) & (NSLOT - 1);
-            P.s[2] = slot;
-            P.cx = tx + 1; P.cy = ty + 1;
-            P.bulk = bulk;
-            const int64_t s = (int64_t)gx_own + (int64_t)L.nx * ((int64_t)gy_own + (int64_t)L.ny * zf);
-            T F[5];
-            site_force<T, L23>(P, m_prev, L, s, F);
-            if (STEP) {
-                T qn[5];
-                P.load5(0, 0, 0, qn);
-#pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    T v2 = fma_t(hdt, F[c], v1_prev[c]);
-                    q_out[c * N + s] = qn[c];
-                    v_out[c * N + s] = v2;
-                    F_out[c * N + s] = F[c];
-                    double fd = (double)F[c], vd = (double)v2;
-                    red[0] = fma(fd, vd, red[0]);
-                    red[1] = fma(fd, fd, red[1]);
-                    red[2] = fma(vd, vd, red[2]);
-                    red[3] = fmax(red[3], fabs(fd));
-                    if (fd != fd) red[3] = fd;
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < 5; ++c) F_out[c * N + s] = F[c];
-            }
-        } else if (own_xy && zf < L.nz) {
-            // sites inside objects carry no degrees of freedom
-            const int64_t s = (int64_t)gx_own + (int64_t)L.nx * ((int64_t)gy_own + (int64_t)L.ny * zf);
-#pragma unroll
-            for (int c = 0; c < 5; ++c) {
-                F_out[c * N + s] = T(0);
-                if (STEP) { q_out[c * N + s] = T(0); v_out[c * N + s] = T(0); }
-            }
-        }
-    }
+    if (L.tile_bulk[bid])
+        march<T, L23, STEP, true>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
+                                  sq, sm, red);
+    else
+        march<T, L23, STEP, false>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
+                                   sq, sm, red);
     if (STEP) grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
 }
 

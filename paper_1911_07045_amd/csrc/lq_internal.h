@@ -34,8 +34,8 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
 
 // Tile geometry of the fused kernel: TX x TY columns, each block marches
 // zc planes.
-constexpr int TX = 64;
-constexpr int TY = 4;
+constexpr int TX = 32;
+constexpr int TY = 8;
 constexpr int NTHREADS = TX * TY;
 
 // Device view of a lattice.
