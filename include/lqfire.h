@@ -197,6 +197,40 @@ int lq_fire_step(lq_lattice* lat, int64_t n_steps, lq_fire_report* out);
 int lq_minimize(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F,
                 void* workspace, int64_t workspace_bytes, lq_fire_report* out);
 
+/* ---- batched FIRE for many small lattices (continuous batching) ----
+ * A batch advances all its member lattices by one FIRE step per kernel
+ * launch; every member keeps its own controller, partial sums and stop test,
+ * so each member follows exactly (bit for bit) the trajectory that
+ * lq_fire_step would give it alone.  Members are added and removed between
+ * lq_batch_step calls, which is how a serving loop admits and retires
+ * requests while others keep running.  All members of a batch share prec
+ * and whether L2/L3 are in use, and live on the batch's device. */
+typedef struct lq_batch lq_batch;
+
+/* capacity: maximum number of members (1 .. 65536).  stream: hipStream_t or
+ * NULL; batch steps run on it. */
+int lq_batch_create(int32_t capacity, void* stream, lq_batch** out);
+int lq_batch_destroy(lq_batch* b);
+
+/* Adds a lattice already bound by lq_fire_init (its stream is synchronized
+ * first).  LQ_EINVAL when the batch is full, the lattice is a member already,
+ * or its prec / L2-L3 use differs from the members'; LQ_ESTATE when it is not
+ * bound. */
+int lq_batch_add(lq_batch* b, lq_lattice* lat);
+
+/* Removes a member; its buffers keep the state of its last step. */
+int lq_batch_remove(lq_batch* b, lq_lattice* lat);
+
+/* Number of members. */
+int32_t lq_batch_size(const lq_batch* b);
+
+/* Runs up to n_steps steps for every member (members that have stopped do
+ * nothing), then leaves each member's state in its bound q, v, F as
+ * lq_fire_step does.  reports: host array of at least lq_batch_size()
+ * entries, filled in the order members were added (removals keep the order
+ * of the rest).  Synchronizes the batch stream. */
+int lq_batch_step(lq_batch* b, int64_t n_steps, lq_fire_report* reports);
+
 /* Message for the last error on lat (or on the calling thread when lat is NULL). */
 const char* lq_last_error(const lq_lattice* lat);
 

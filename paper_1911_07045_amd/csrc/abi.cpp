@@ -507,3 +507,159 @@ int lq_minimize(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, voi
 const char* lq_last_error(const lq_lattice* lat) { return lat ? lat->err.c_str() : g_err.c_str(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches
+struct lq_batch {
+    int capacity = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<lq_lattice*> members;
+    int prec = -1;
+    bool l23 = false;
+    MemberDev* d_mem = nullptr;
+    int* d_tile_off = nullptr;
+    int* d_fin_off = nullptr;
+    FireDev* d_gather = nullptr;
+    MemberDev* h_mem = nullptr;  // pinned
+    int* h_off = nullptr;        // pinned: tile offsets then finalize offsets
+    FireDev* h_gather = nullptr; // pinned
+    int total_tiles = 0, total_fin = 0;
+};
+
+static int fin_blocks_of(const lq_lattice* lat) {
+    const int64_t n = 5 * lat->N;
+    const int64_t b = (n + 256 * 8 - 1) / (256 * 8);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
+}
+
+extern "C" {
+
+int lq_batch_create(int32_t capacity, void* stream, lq_batch** out) {
+    if (!out) return fail(nullptr, LQ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (capacity < 1 || capacity > 65536) return fail(nullptr, LQ_EINVAL, "capacity out of range");
+    lq_batch* b = new lq_batch();
+    b->capacity = capacity;
+    b->stream = (hipStream_t)stream;
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) e = hipMalloc(&b->d_mem, sizeof(MemberDev) * capacity);
+    if (e == hipSuccess) e = hipMalloc(&b->d_tile_off, sizeof(int) * (capacity + 1));
+    if (e == hipSuccess) e = hipMalloc(&b->d_fin_off, sizeof(int) * (capacity + 1));
+    if (e == hipSuccess) e = hipMalloc(&b->d_gather, sizeof(FireDev) * capacity);
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_mem, sizeof(MemberDev) * capacity, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_off, sizeof(int) * 2 * (capacity + 1), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_gather, sizeof(FireDev) * capacity, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        lq_batch_destroy(b);
+        return fail(nullptr, LQ_ENOMEM, std::string("batch allocation failed: ") + hipGetErrorString(e));
+    }
+    *out = b;
+    return LQ_OK;
+}
+
+int lq_batch_destroy(lq_batch* b) {
+    if (!b) return LQ_OK;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    if (b->d_mem) (void)hipFree(b->d_mem);
+    if (b->d_tile_off) (void)hipFree(b->d_tile_off);
+    if (b->d_fin_off) (void)hipFree(b->d_fin_off);
+    if (b->d_gather) (void)hipFree(b->d_gather);
+    if (b->h_mem) (void)hipHostFree(b->h_mem);
+    if (b->h_off) (void)hipHostFree(b->h_off);
+    if (b->h_gather) (void)hipHostFree(b->h_gather);
+    delete b;
+    return LQ_OK;
+}
+
+int32_t lq_batch_size(const lq_batch* b) { return b ? (int32_t)b->members.size() : 0; }
+
+int lq_batch_add(lq_batch* b, lq_lattice* lat) {
+    if (!b || !lat) return fail(lat, LQ_EINVAL, "batch or lattice is NULL");
+    if (!lat->bound) return fail(lat, LQ_ESTATE, "lattice is not bound by lq_fire_init");
+    if ((int)b->members.size() >= b->capacity) return fail(lat, LQ_EINVAL, "batch is full");
+    if (lat->device != b->device) return fail(lat, LQ_EINVAL, "lattice and batch are on different devices");
+    for (lq_lattice* m : b->members)
+        if (m == lat) return fail(lat, LQ_EINVAL, "lattice is a member already");
+    if (!b->members.empty() && (lat->p.prec != b->prec || lat->l23 != b->l23))
+        return fail(lat, LQ_EINVAL, "members must share prec and the use of L2/L3");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    if (b->members.empty()) {
+        b->prec = lat->p.prec;
+        b->l23 = lat->l23;
+    }
+    b->members.push_back(lat);
+    return LQ_OK;
+}
+
+int lq_batch_remove(lq_batch* b, lq_lattice* lat) {
+    if (!b || !lat) return fail(lat, LQ_EINVAL, "batch or lattice is NULL");
+    for (size_t i = 0; i < b->members.size(); ++i)
+        if (b->members[i] == lat) {
+            b->members.erase(b->members.begin() + (long)i);
+            return LQ_OK;
+        }
+    return fail(lat, LQ_EINVAL, "lattice is not a member");
+}
+
+int lq_batch_step(lq_batch* b, int64_t n_steps, lq_fire_report* reports) {
+    if (!b) return fail(nullptr, LQ_EINVAL, "batch is NULL");
+    if (n_steps < 0) return fail(nullptr, LQ_EINVAL, "n_steps < 0");
+    const int n = (int)b->members.size();
+    if (n == 0) return LQ_OK;
+    if (!reports) return fail(nullptr, LQ_EINVAL, "reports is NULL");
+    HIPCHK(nullptr, hipSetDevice(b->device));
+    for (lq_lattice* m : b->members)
+        if (!m->bound) return fail(nullptr, LQ_ESTATE, "a member lost its FIRE binding; remove it or bind it again");
+    // the descriptors are rebuilt on every call (a few hundred bytes per
+    // member), so members re-bound by lq_fire_init are picked up
+    {
+        int t = 0, f = 0;
+        for (int i = 0; i < n; ++i) {
+            lq_lattice* m = b->members[i];
+            MemberDev& d = b->h_mem[i];
+            std::memset(&d, 0, sizeof(d));
+            d.L = m->dev;
+            const Bufs<double>& bb = m->b64;
+            for (int k = 0; k < 2; ++k) {
+                d.q[k] = bb.q[k];
+                d.v[k] = bb.v[k];
+                d.F[k] = bb.F[k];
+            }
+            d.partials = m->d_partials;
+            d.st = m->d_state;
+            d.nblocks = (int)n_step_blocks(m->dev);
+            b->h_off[i] = t;
+            b->h_off[(b->capacity + 1) + i] = f;
+            t += d.nblocks;
+            f += fin_blocks_of(m);
+        }
+        b->h_off[n] = t;
+        b->h_off[(b->capacity + 1) + n] = f;
+        b->total_tiles = t;
+        b->total_fin = f;
+        HIPCHK(nullptr, hipMemcpyAsync(b->d_mem, b->h_mem, sizeof(MemberDev) * n, hipMemcpyHostToDevice, b->stream));
+        HIPCHK(nullptr, hipMemcpyAsync(b->d_tile_off, b->h_off, sizeof(int) * (n + 1), hipMemcpyHostToDevice,
+                                       b->stream));
+        HIPCHK(nullptr, hipMemcpyAsync(b->d_fin_off, b->h_off + (b->capacity + 1), sizeof(int) * (n + 1),
+                                       hipMemcpyHostToDevice, b->stream));
+    }
+    int rc = launch_batch_steps(b->prec, b->l23, b->d_mem, b->d_tile_off, n, b->total_tiles, b->d_fin_off,
+                                b->total_fin, b->d_gather, n_steps, b->stream);
+    if (rc != LQ_OK) return fail(nullptr, rc, "batch kernel launch failed");
+    HIPCHK(nullptr, hipMemcpyAsync(b->h_gather, b->d_gather, sizeof(FireDev) * n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(nullptr, hipStreamSynchronize(b->stream));
+    int worst = LQ_OK;
+    for (int i = 0; i < n; ++i) {
+        fill_report(b->h_gather[i], &reports[i]);
+        *b->members[i]->h_state = b->h_gather[i];
+        if (b->h_gather[i].status == LQ_NONFINITE) worst = LQ_ENONFINITE;
+    }
+    if (worst != LQ_OK) return fail(nullptr, worst, "a member's FIRE reduction is not finite");
+    return LQ_OK;
+}
+
+}  // extern "C"

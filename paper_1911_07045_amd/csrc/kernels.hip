@@ -68,6 +68,13 @@ __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t voff, uin
     }
 }
 
+// Barrier for data exchanged through LDS only: waits for this wave's LDS
+// operations, not for its global loads and stores (which __syncthreads()
+// would drain, stalling every plane on memory latency).
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ int wrapc(int g, int n, int per) {
     if (g >= 0 && g < n) return g;
     if (!per) return -1;
@@ -523,31 +530,30 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
     const __amdgpu_buffer_rsrc_t rq_out = field_rsrc(STEP ? q_out : F_out, fb);
     const __amdgpu_buffer_rsrc_t rv_out = field_rsrc(STEP ? v_out : F_out, fb);
     const __amdgpu_buffer_rsrc_t rF_out = field_rsrc(F_out, fb);
+    const __amdgpu_buffer_rsrc_t rmask = field_rsrc(L.mask, (uint32_t)N);
+    constexpr uint32_t NONE = 0xFFFFFFFFu;  // past every resource: loads give 0, stores drop
+    // Branch-free loads: an invalid position gets an offset past the end of the
+    // buffer instead of a branch, so the wait counts stay exact and the stores
+    // of the previous plane can drain while this plane is drifted.
     auto load = [&](int i) {
-        const int wz = wrapc(z0 - 1 + i, L.nz, L.per[2]);
-        const int s = (sxy_own >= 0 && wz >= 0) ? sxy_own + nxy * wz : -1;
+        const int wz = (i >= 0 && i <= zc + 1) ? wrapc(z0 - 1 + i, L.nz, L.per[2]) : -1;
+        const bool ok = sxy_own >= 0 && wz >= 0;
+        const uint32_t site = (uint32_t)(sxy_own + nxy * wz);
+        const uint32_t off = ok ? site * (uint32_t)sizeof(T) : NONE;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) { rq[c] = T(0); rv[c] = T(0); rf[c] = T(0); }
-        rm = 0;
-        if (s >= 0) {
-            const uint32_t off = (uint32_t)s * (uint32_t)sizeof(T);
-#pragma unroll
-            for (int c = 0; c < 5; ++c) {
-                rq[c] = bld<T>(rq_in, off, c * cs);
-                if (STEP) { rv[c] = bld<T>(rv_in, off, c * cs); rf[c] = bld<T>(rF_in, off, c * cs); }
-            }
-            if (!BULK) rm = L.mask[s];
+        for (int c = 0; c < 5; ++c) {
+            rq[c] = bld<T>(rq_in, off, c * cs);
+            if (STEP) { rv[c] = bld<T>(rv_in, off, c * cs); rf[c] = bld<T>(rF_in, off, c * cs); }
         }
+        if (!BULK) rm = __builtin_amdgcn_raw_buffer_load_b8(rmask, (int)(ok ? site : NONE), 0, 0);
 #pragma unroll
         for (int j = 0; j < ITEMS_PER_THREAD; ++j) {
-            iq[j] = T(0); iv[j] = T(0); iF[j] = T(0); im[j] = 0;
-            const int t = (it_sxy[j] >= 0 && wz >= 0) ? it_sxy[j] + nxy * wz : -1;
-            if (t >= 0) {
-                const uint32_t off = ((uint32_t)it_c[j] * (uint32_t)N + (uint32_t)t) * (uint32_t)sizeof(T);
-                iq[j] = bld<T>(rq_in, off, 0u);
-                if (STEP) { iv[j] = bld<T>(rv_in, off, 0u); iF[j] = bld<T>(rF_in, off, 0u); }
-                if (!BULK && it_c[j] == 0) im[j] = L.mask[t];
-            }
+            const bool okj = it_sxy[j] >= 0 && wz >= 0;
+            const uint32_t t = (uint32_t)(it_sxy[j] + nxy * wz);
+            const uint32_t offj = okj ? ((uint32_t)it_c[j] * (uint32_t)N + t) * (uint32_t)sizeof(T) : NONE;
+            iq[j] = bld<T>(rq_in, offj, 0u);
+            if (STEP) { iv[j] = bld<T>(rv_in, offj, 0u); iF[j] = bld<T>(rF_in, offj, 0u); }
+            if (!BULK) im[j] = __builtin_amdgcn_raw_buffer_load_b8(rmask, (int)(okj && it_c[j] == 0 ? t : NONE), 0, 0);
         }
     };
     // drift the registers into LDS slot; returns the own site's q' and v1
@@ -578,75 +584,75 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
             if (!BULK && it_c[j] == 0) sm[slot][it_py[j]][it_px[j]] = (uint8_t)im[j];
         }
     };
-    auto slot_of = [](int i) { return i & (NS - 1); };
+    auto slot_of = [](int i) { return (i + NS) & (NS - 1); };
 
-    T v1_cur[5], v1_next[5], q_unused[5], v1_unused[5];
-    uint32_t m_cur, m_next, m_unused;
-    load(0);
-    drift(slot_of(0), q_unused, v1_unused, m_unused);
-    load(1);
-    drift(slot_of(1), q_unused, v1_cur, m_cur);
-    load(2);
-    for (int f = 1; f <= zc; ++f) {
-        drift(slot_of(f + 1), q_unused, v1_next, m_next);
-        if (f + 2 <= zc + 1) load(f + 2);
-        __syncthreads();
-        if (own_xy) {
+    // One loop body issues every global access, so the hardware wait counts
+    // are exact on all paths: iteration k drifts plane k (loaded by
+    // iteration k-1), loads plane k+1, and evaluates the force of plane k-1.
+    // Planes outside 0 .. zc+1 are loaded with out-of-range offsets and the
+    // force outside 1 .. zc is stored nowhere.
+#pragma unroll
+    for (int c = 0; c < 5; ++c) { rq[c] = T(0); rv[c] = T(0); rf[c] = T(0); }
+#pragma unroll
+    for (int j = 0; j < ITEMS_PER_THREAD; ++j) { iq[j] = T(0); iv[j] = T(0); iF[j] = T(0); im[j] = 0; }
+    T v1_prev[5], v1_cur[5], q_unused[5];
+    uint32_t m_prev = 0, m_cur = 0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) { v1_prev[c] = T(0); v1_cur[c] = T(0); }
+    for (int k = -1; k <= zc + 1; ++k) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) v1_prev[c] = v1_cur[c];
+        m_prev = m_cur;
+        drift(slot_of(k), q_unused, v1_cur, m_cur);
+        load(k + 1);
+        lds_barrier();
+        {
+            const int f = k - 1;  // plane whose force is evaluated
+            const bool in_chunk = f >= 1;
             const int s = gx + L.nx * gy + nxy * (z0 + f - 1);
-            const uint32_t off = (uint32_t)s * (uint32_t)sizeof(T);
-            if (m_cur & M_SIM) {
-                Stencil<T, L23, BULK> P;
-                P.q = sq; P.m = sm;
-                P.s[0] = slot_of(f - 1); P.s[1] = slot_of(f); P.s[2] = slot_of(f + 1);
-                P.cx = tx + 1; P.cy = ty + 1;
-                T F[5];
-                site_force<T, L23, BULK>(P, m_cur, L, s, F);
+            const uint32_t off = (own_xy && in_chunk) ? (uint32_t)s * (uint32_t)sizeof(T) : NONE;
+            const bool live = own_xy && in_chunk && (m_prev & M_SIM);
+            Stencil<T, L23, BULK> P;
+            P.q = sq; P.m = sm;
+            P.s[0] = slot_of(f - 1); P.s[1] = slot_of(f); P.s[2] = slot_of(f + 1);
+            P.cx = tx + 1; P.cy = ty + 1;
+            T F[5];
+            site_force<T, L23, BULK>(P, m_prev, L, s, F);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                const T Fc = live ? F[c] : T(0);
                 if (STEP) {
-#pragma unroll
-                    for (int c = 0; c < 5; ++c) {
-                        const T v2 = fma_t(hdt, F[c], v1_cur[c]);
-                        bst<T>(rq_out, off, c * cs, P.at(0, 0, 0, c));
-                        bst<T>(rv_out, off, c * cs, v2);
-                        bst<T>(rF_out, off, c * cs, F[c]);
-                        const double fd = (double)F[c], vd = (double)v2;
-                        red[0] = fma(fd, vd, red[0]);
-                        red[1] = fma(fd, fd, red[1]);
-                        red[2] = fma(vd, vd, red[2]);
-                        red[3] = fmax(red[3], fabs(fd));
-                    }
+                    const T v2 = live ? fma_t(hdt, F[c], v1_prev[c]) : T(0);
+                    const T qc = live ? P.at(0, 0, 0, c) : T(0);
+                    bst<T>(rq_out, off, c * cs, qc);
+                    bst<T>(rv_out, off, c * cs, v2);
+                    bst<T>(rF_out, off, c * cs, Fc);
+                    const double fd = (double)Fc, vd = (double)v2;
+                    red[0] = fma(fd, vd, red[0]);
+                    red[1] = fma(fd, fd, red[1]);
+                    red[2] = fma(vd, vd, red[2]);
+                    red[3] = fmax(red[3], fabs(fd));
                 } else {
-#pragma unroll
-                    for (int c = 0; c < 5; ++c) bst<T>(rF_out, off, c * cs, F[c]);
-                }
-            } else {
-                // sites inside objects carry no degrees of freedom
-#pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    bst<T>(rF_out, off, c * cs, T(0));
-                    if (STEP) { bst<T>(rq_out, off, c * cs, T(0)); bst<T>(rv_out, off, c * cs, T(0)); }
+                    bst<T>(rF_out, off, c * cs, Fc);
                 }
             }
         }
-#pragma unroll
-        for (int c = 0; c < 5; ++c) v1_cur[c] = v1_next[c];
-        m_cur = m_next;
     }
 }
 
+// One block of the force / FIRE step: tile `bid` of lattice L.  `nblocks`
+// is the lattice's own tile count; partials are indexed by tile, so the
+// reduction order does not depend on how blocks are dispatched.
 template <typename T, bool L23, bool STEP>
-__global__ __launch_bounds__(NTHREADS) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
-                                                    T* __restrict__ Fout, double* partials,
-                                                    FireDev* st) {
+__device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, const T* __restrict__ qin,
+                                           T* __restrict__ Fout, double* partials, FireDev* st,
+                                           int nblocks, int bid) {
     constexpr int NS = 4;
     __shared__ T sq[NS][5][PY][PX];
     __shared__ uint8_t sm[NS][PY][PX];
     __shared__ double scratch[NTHREADS / 64][4];
     __shared__ int last_flag;
 
-    const int nblocks = (int)gridDim.x;
-    int bid = (int)blockIdx.x;
-    // keep neighbouring tiles on one XCD: dispatch is round-robin over 8 XCDs
-    if ((nblocks & 7) == 0) bid = (bid & 7) * (nblocks >> 3) + (bid >> 3);
     const int bx = bid % L.ntx, by = (bid / L.ntx) % L.nty, bz = bid / (L.ntx * L.nty);
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * L.zc;
     const int zc = min(L.zc, L.nz - z0);
@@ -674,6 +680,91 @@ __global__ __launch_bounds__(NTHREADS) void k_march(LatDev L, Bufs<T> b, const T
         march<T, L23, STEP, false>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
                                    sq, sm, red);
     if (STEP) grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
+}
+
+template <typename T, bool L23, bool STEP>
+__global__ __launch_bounds__(NTHREADS) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
+                                                    T* __restrict__ Fout, double* partials,
+                                                    FireDev* st) {
+    const int nblocks = (int)gridDim.x;
+    int bid = (int)blockIdx.x;
+    // keep neighbouring tiles on one XCD: dispatch is round-robin over 8 XCDs
+    if ((nblocks & 7) == 0) bid = (bid & 7) * (nblocks >> 3) + (bid >> 3);
+    step_block<T, L23, STEP>(L, b, qin, Fout, partials, st, nblocks, bid);
+}
+
+// ---------------------------------------------------------------------------
+// Batched steps: one launch advances every member of a batch of lattices by
+// one FIRE step.  Block b belongs to the member m with off[m] <= b <
+// off[m+1]; each member keeps its own controller, partials and ticket, so
+// its trajectory is bit for bit the one it has alone.
+__device__ __forceinline__ int member_of(const int* __restrict__ off, int n, int b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, bool L23>
+__global__ __launch_bounds__(NTHREADS) void k_march_batch(const MemberDev* __restrict__ mem,
+                                                          const int* __restrict__ off, int n_members) {
+    const int m = member_of(off, n_members, (int)blockIdx.x);
+    const MemberDev& M = mem[m];
+    Bufs<T> b;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        b.q[i] = (T*)M.q[i]; b.v[i] = (T*)M.v[i]; b.F[i] = (T*)M.F[i];
+    }
+    const LatDev L = M.L;
+    step_block<T, L23, true>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
+                             (int)blockIdx.x - off[m]);
+}
+
+__global__ void k_batch_begin(const MemberDev* __restrict__ mem, int n_members, int64_t n_steps) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n_members) return;
+    FireDev* st = mem[m].st;
+    if (st->status == LQ_RUNNING) {
+        st->done = 0;
+        st->stop_at = st->step + n_steps;
+        if (n_steps <= 0) st->done = 1;
+    }
+}
+
+// State of every member into its buffer 0 with pending steering applied.
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_finalize(const MemberDev* __restrict__ mem,
+                                                        const int* __restrict__ off, int n_members) {
+    const int m = member_of(off, n_members, (int)blockIdx.x);
+    const MemberDev& M = mem[m];
+    const FireDev* st = M.st;
+    const int cur = st->cur;
+    const T cv = T(st->c_v), cF = T(st->c_F);
+    const int64_t n = 5 * M.L.N;
+    const int nb = off[m + 1] - off[m];
+    T* q0 = (T*)M.q[0]; T* v0 = (T*)M.v[0]; T* F0 = (T*)M.F[0];
+    const T* qc = (const T*)M.q[cur]; const T* vc = (const T*)M.v[cur]; const T* Fc = (const T*)M.F[cur];
+    for (int64_t i = ((int)blockIdx.x - off[m]) * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)nb * blockDim.x) {
+        const T v = vc[i], f = Fc[i];
+        const T vm = fma_t(cv, v, cF * f);
+        if (cur) { q0[i] = qc[i]; F0[i] = f; }
+        v0[i] = vm;
+    }
+}
+
+// Resets the pending steering of every member and gathers the controller
+// states into one array for a single copy to the host.
+__global__ void k_batch_reset_gather(const MemberDev* __restrict__ mem, int n_members, FireDev* out) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n_members) return;
+    FireDev* st = mem[m].st;
+    st->cur = 0;
+    st->c_v = 1.0;
+    st->c_F = 0.0;
+    out[m] = *st;
 }
 
 // ---------------------------------------------------------------------------
@@ -973,6 +1064,30 @@ int launch_uniaxial(const LatDev& L, int prec, const double* dirs, double S, voi
     hipStream_t s = (hipStream_t)stream;
     if (prec == LQ_F64) k_uniaxial<double><<<grid_1d(L.N), 256, 0, s>>>(L, dirs, S, (double*)q);
     else k_uniaxial<float><<<grid_1d(L.N), 256, 0, s>>>(L, dirs, S, (float*)q);
+    return hip_status(hipGetLastError());
+}
+
+int launch_batch_steps(int prec, bool l23, const MemberDev* mem, const int* tile_off, int n_members,
+                       int total_tiles, const int* fin_off, int total_fin, FireDev* gather, int64_t n_steps,
+                       void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = (n_members + 63) / 64;
+    k_batch_begin<<<nb, 64, 0, s>>>(mem, n_members, n_steps);
+    if (hipGetLastError() != hipSuccess) return LQ_EHIP;
+    for (int64_t i = 0; i < n_steps; ++i) {
+        if (prec == LQ_F64) {
+            if (l23) k_march_batch<double, true><<<total_tiles, NTHREADS, 0, s>>>(mem, tile_off, n_members);
+            else k_march_batch<double, false><<<total_tiles, NTHREADS, 0, s>>>(mem, tile_off, n_members);
+        } else {
+            if (l23) k_march_batch<float, true><<<total_tiles, NTHREADS, 0, s>>>(mem, tile_off, n_members);
+            else k_march_batch<float, false><<<total_tiles, NTHREADS, 0, s>>>(mem, tile_off, n_members);
+        }
+        if (hipGetLastError() != hipSuccess) return LQ_EHIP;
+    }
+    if (prec == LQ_F64) k_batch_finalize<double><<<total_fin, 256, 0, s>>>(mem, fin_off, n_members);
+    else k_batch_finalize<float><<<total_fin, 256, 0, s>>>(mem, fin_off, n_members);
+    if (hipGetLastError() != hipSuccess) return LQ_EHIP;
+    k_batch_reset_gather<<<nb, 64, 0, s>>>(mem, n_members, gather);
     return hip_status(hipGetLastError());
 }
 

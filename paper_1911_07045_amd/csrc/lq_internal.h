@@ -75,6 +75,18 @@ struct Bufs {
     T* F[2];
 };
 
+// One member of a batch (device copy).
+struct MemberDev {
+    LatDev L;
+    void* q[2];
+    void* v[2];
+    void* F[2];
+    double* partials;
+    FireDev* st;
+    int nblocks;  // step tiles of this member
+    int pad;
+};
+
 struct EnergyOut {
     double bulk, elastic, anch;
 };
@@ -92,6 +104,9 @@ int launch_energy(const LatDev& L, bool l23, int prec, const void* q, double* pa
                   EnergyOut* out, uint32_t* ticket, void* stream);
 int launch_uniaxial(const LatDev& L, int prec, const double* dirs, double S, void* q,
                     void* stream);
+int launch_batch_steps(int prec, bool l23, const MemberDev* mem, const int* tile_off, int n_members,
+                       int total_tiles, const int* fin_off, int total_fin, FireDev* gather, int64_t n_steps,
+                       void* stream);
 int64_t n_step_blocks(const LatDev& L);
 int64_t n_energy_blocks(const LatDev& L);
 

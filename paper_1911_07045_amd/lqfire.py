@@ -101,6 +101,12 @@ def lib():
             "lq_minimize": (C.c_int, [vp, C.POINTER(FireParams), vp, vp, vp, vp, i64,
                                       C.POINTER(FireReport)]),
             "lq_last_error": (C.c_char_p, [vp]),
+            "lq_batch_create": (C.c_int, [i32, vp, C.POINTER(vp)]),
+            "lq_batch_destroy": (C.c_int, [vp]),
+            "lq_batch_add": (C.c_int, [vp, vp]),
+            "lq_batch_remove": (C.c_int, [vp, vp]),
+            "lq_batch_size": (i32, [vp]),
+            "lq_batch_step": (C.c_int, [vp, i64, C.POINTER(FireReport)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -305,6 +311,50 @@ class Lattice:
                                  ws.numel() - off, C.byref(r)), self.h)
         self._bound = (q, v, F)
         return r, q, v, F
+
+
+class Batch:
+    """lq_batch: many bound lattices advanced by one launch per FIRE step."""
+
+    def __init__(self, capacity=256, stream=None):
+        import torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().lq_batch_create(int(capacity), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.capacity = int(capacity)
+        self.members = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lq_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.members)
+
+    def add(self, lat: Lattice):
+        _check(lib().lq_batch_add(self.h, lat.h), lat.h)
+        self.members.append(lat)
+
+    def remove(self, lat: Lattice):
+        _check(lib().lq_batch_remove(self.h, lat.h), lat.h)
+        self.members.remove(lat)
+
+    def step(self, n_steps):
+        """Returns one FireReport per member, in member order."""
+        n = len(self.members)
+        reps = (FireReport * max(n, 1))()
+        rc = lib().lq_batch_step(self.h, int(n_steps), reps)
+        if rc not in (LQ_OK, LQ_ENONFINITE):
+            _check(rc)
+        return [reps[i] for i in range(n)]
 
 
 # ---- the ABI names, as plain functions ----
