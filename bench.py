@@ -134,6 +134,70 @@ def cpu_leg(cfg):
                        f"2^3 difference choices, gcc -O2, OpenMP over z-planes)")
 
 
+def precision_leg(cfg, steps=2000, polish=200):
+    """FP32 state with FP64 reductions for `steps` FIRE steps, then an FP64
+    polish of `polish` steps from the FP32 state, against an FP64 run of
+    steps + polish from the same start.  The FP64 GPU path stands in for the
+    oracle at this size (it matches the oracle's per-step forces to 1e-10)."""
+    import numpy as np
+    import torch
+
+    from paper_1911_07045_amd import lqfire, synth
+
+    nx, ny, nz = cfg["shape"]
+    N = nx * ny * nz
+    dirs = torch.from_numpy(np.ascontiguousarray(synth.random_directors(cfg["dir_seed"], N))).cuda()
+    out = {}
+    t0 = time.perf_counter()
+    lat32 = lqfire.lattice_from_config(cfg, prec="f32")
+    q32 = lat32.set_uniaxial(dirs, lat32.empty())
+    v32, F32 = lat32.empty(), lat32.empty()
+    lat32.fire_init(lqfire.fire_params_from_config(cfg, force_tol=0.0, max_steps=steps), q32, v32, F32)
+    r32 = lat32.fire_step(steps)
+    e32 = lat32.energy(q32)["total"]
+    qp = q32.double().contiguous()
+    del v32, F32
+    lat32.close()
+    lat64 = lqfire.lattice_from_config(cfg, prec="f64")
+    vp, Fp = lat64.empty(), lat64.empty()
+    lat64.fire_init(lqfire.fire_params_from_config(cfg, force_tol=0.0, max_steps=polish), qp, vp, Fp)
+    rp = lat64.fire_step(polish)
+    ep = lat64.energy(qp)["total"]
+    del vp, Fp
+    qr = lat64.set_uniaxial(dirs, lat64.empty())
+    vr, Fr = lat64.empty(), lat64.empty()
+    lat64.fire_init(lqfire.fire_params_from_config(cfg, force_tol=0.0, max_steps=steps + polish), qr, vr, Fr)
+    rr = lat64.fire_step(steps + polish)
+    er = lat64.energy(qr)["total"]
+    dq = (qp - qr).abs().max().item()
+    dq32 = (q32.double() - qr).abs().max().item()
+    out = {"schedule": f"{steps} FP32 steps + {polish} FP64 polish vs {steps + polish} FP64 steps",
+           "reference": "FP64 GPU path from the same start",
+           "max_abs_dQ_polished": dq, "max_abs_dQ_fp32_state": dq32,
+           "rel_energy_err_polished": abs(ep - er) / abs(er), "rel_energy_err_fp32": abs(e32 - er) / abs(er),
+           "maxF_fp32": r32.maxF, "maxF_polished": rp.maxF, "maxF_fp64": rr.maxF,
+           "energy_fp64": er, "seconds": time.perf_counter() - t0}
+    return out
+
+
+def serving_leg(n_requests=512, rate=20.0):
+    """The continuous-batching server on a Poisson stream of small boxes."""
+    import torch
+
+    from paper_1911_07045_amd import serve, synth
+
+    reqs = synth.serving_stream(n_requests=n_requests, rate=rate)
+    srv = serve.Server(max_members=64, chunk=50)
+    results = srv.run(reqs, realtime=True)
+    out = serve.summarize(results, srv.wall_s, srv.busy_s)
+    out.update({"stream": f"{n_requests} requests, Poisson {rate}/s, side log-U[16,64], one colloid, "
+                          f"W_RP log-U[0.1,10], FP32, tol 1e-5 or 5000 steps",
+                "max_members": 64, "chunk_steps": 50,
+                "hbm_budget_GB": srv.budget / 1e9})
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +205,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="multi_colloid256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs one GPU only: the hot path here is a single-GPU lattice "
@@ -175,6 +242,12 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
         "energy_start_end": [g["E0"], g["E1"]],
     }
+    if not args.no_precision and cfg["prec"] == "f32":
+        print("[bench] precision form", file=sys.stderr, flush=True)
+        out["precision"] = precision_leg(cfg)
+    if not args.no_serving:
+        print("[bench] serving stream", file=sys.stderr, flush=True)
+        out["serving"] = serving_leg(args.serving_requests)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_leg(cfg)

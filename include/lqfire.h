@@ -37,7 +37,7 @@ extern "C" {
 /* ---- return codes ---- */
 #define LQ_OK 0
 #define LQ_EINVAL (-1)        /* bad argument: sizes, pointers, NaN/negative parameters */
-#define LQ_EUNSUPPORTED (-2)  /* valid in the paper but not built: L4, L6, W_RP < 0 */
+#define LQ_EUNSUPPORTED (-2)  /* valid in the paper but not built: L4, L6 */
 #define LQ_ENOMEM (-3)        /* workspace too small, or a device allocation failed */
 #define LQ_EHIP (-4)          /* a HIP runtime call failed */
 #define LQ_ENONFINITE (-5)    /* a FIRE reduction produced NaN or Inf */
@@ -76,7 +76,11 @@ double lq_bulk_S0(const lq_lattice* lat);
 #define LQ_OBJ_PATTERNED_WALL 3 /* a wall whose preferred director is the in-plane radial unit
                                    vector away from the nearest centre of a square array */
 #define LQ_LAW_ND 0             /* W is the Nobili-Durand strength of W tr((Q - Q0)^2) */
-#define LQ_LAW_RP 1             /* W is a Rapini-Papoular strength; used as W / (9 S0^2) */
+#define LQ_LAW_RP 1             /* W is a Rapini-Papoular strength: W >= 0 is used as the
+                                   Nobili-Durand strength W / (9 S0^2); W < 0 (degenerate
+                                   planar) as the Fournier-Galatola strength |W| / (9 S0^2) */
+#define LQ_LAW_FG 2             /* W is the Fournier-Galatola strength of Eq. (planarDegenerate),
+                                   W |Qt - P Qt P|^2, Qt = Q + S0/2 I, P = I - nu nu */
 #define LQ_DIR_NORMAL 0         /* preferred director = surface normal (homeotropic) */
 #define LQ_DIR_FIXED 1          /* preferred director = dir (oriented anchoring) */
 
@@ -86,7 +90,7 @@ typedef struct {
     int32_t dir_mode;  /* LQ_DIR_* (ignored by LQ_OBJ_PATTERNED_WALL) */
     int32_t axis;      /* wall axis 0, 1, 2 */
     int64_t plane;     /* wall plane index, 0 <= plane < n[axis] */
-    double W;          /* strength >= 0; W_RP < 0 (degenerate planar) is LQ_EUNSUPPORTED */
+    double W;          /* strength >= 0 (a Rapini-Papoular strength may be negative) */
     double center[3];  /* sphere centre (lattice units, any real value) */
     double radius;     /* sphere radius > 0 */
     double dir[3];     /* fixed preferred director (normalized by the library) */
@@ -95,11 +99,13 @@ typedef struct {
     int32_t count[2];  /* patterned wall: centres per in-plane axis */
 } lq_object;
 
-/* One extra anchoring term W tr((Q - Q0(n0))^2) at a simulated site: the
- * paper's arbitrary per-site anchoring (its custom boundary files). */
+/* One extra anchoring term at a simulated site: the paper's arbitrary
+ * per-site anchoring (its custom boundary files).  For a Nobili-Durand term
+ * n0 is the preferred director; for a Fournier-Galatola term (LQ_LAW_FG, or
+ * LQ_LAW_RP with W < 0) it is the surface normal nu. */
 typedef struct {
     int64_t site;
-    int32_t law; /* LQ_LAW_ND or LQ_LAW_RP */
+    int32_t law; /* LQ_LAW_* */
     int32_t pad;
     double W;
     double n0[3];
@@ -109,7 +115,10 @@ typedef struct {
  * inside an object (not simulated); object_sites marks extra ones.  A
  * simulated site with a face neighbour inside object a carries one anchoring
  * term of a (so a site touching two objects carries two); recs add more.
- * Anchoring uses Q0 = 3/2 S0 (n0 n0 - I/3).  Host arrays; any may be NULL
+ * Nobili-Durand anchoring uses Q0 = 3/2 S0 (n0 n0 - I/3); Fournier-Galatola
+ * anchoring uses the surface normal nu of the object (the wall axis, or the
+ * unit vector from a sphere's centre) and ignores dir_mode and the patterned
+ * wall's radial director (sec. II.D).  Host arrays; any may be NULL
  * when its count is 0.  LQ_EINVAL on a bad object, a record at an object site
  * or out of range, or S0 not real while anchoring is requested. */
 int lq_set_boundaries(lq_lattice* lat, const lq_object* objs, int32_t n_objs,
@@ -119,9 +128,13 @@ int lq_set_boundaries(lq_lattice* lat, const lq_object* objs, int32_t n_objs,
 /* Host-only form of the same rasterization (needs no GPU).  Writes the site
  * type of every site to types (N bytes: 0 bulk, 1 boundary, 2 object; may be
  * NULL) and, per anchored site in increasing site order, anch_site[i] and
- * anch_data[7*i .. 7*i+6] = {sum W, sum W*Q0 (5 q-components),
- * sum W*tr(Q0^2)}; at most cap entries are written (arrays may be NULL when
- * cap is 0).  *n_anchored receives the full count. */
+ * the site's anchoring energy as a quadratic form in its five components,
+ * f = 1/2 q^T K q + b^T q + c (every anchoring term is quadratic in Q):
+ * anch_data[LQ_ANCH_STRIDE*i ...] = {K00, K01, .., K04, K11, .., K44 (upper
+ * triangle, row by row, 15 values), b (5 values), c}; at most cap entries
+ * are written (arrays may be NULL when cap is 0).  *n_anchored receives the
+ * full count. */
+#define LQ_ANCH_STRIDE 21
 int lq_rasterize(const lq_params* p, const lq_object* objs, int32_t n_objs,
                  const lq_site_anchor* recs, int64_t n_recs, const int64_t* object_sites,
                  int64_t n_object_sites, uint8_t* types, int64_t* n_anchored,
@@ -135,12 +148,23 @@ int lq_set_uniaxial(lq_lattice* lat, const double* directors, double S, void* q)
 
 /* F = -dE/dq of the discrete energy: bulk Eq. (fphase), distortion
  * Eq. (fdistortionFull) with one-sided differences Eq. (onesidedderivatives)
- * averaged over every allowed choice per axis, and anchoring.  F = 0 inside
+ * averaged over every allowed choice per axis, anchoring and external
+ * fields.  F = 0 inside
  * objects.  q and F: device, 5*N elements. */
 int lq_compute_forces(lq_lattice* lat, const void* q, void* F);
 
+/* External fields (sec. II.C, external fields free energy): each field
+ * adds -(chi/3) h_i Q_ij h_j at every simulated site, where h is the field
+ * vector and chi the product of the vacuum constant and the anisotropic
+ * susceptibility (mu0 dchi for H, eps0 deps for E), in units of |A|.
+ * h: host, [n_fields][3]; chi: host, [n_fields].  Replaces the fields set
+ * before; n_fields = 0 removes them.  Like lq_set_boundaries it changes the
+ * energy, so a bound FIRE state must be initialized again (LQ_ESTATE
+ * otherwise).  LQ_EINVAL on non-finite values or n_fields < 0. */
+int lq_set_field(lq_lattice* lat, const double* h, const double* chi, int32_t n_fields);
+
 typedef struct {
-    double bulk, elastic, anchoring, total;
+    double bulk, elastic, anchoring, external, total;
     int64_t n_sim; /* simulated sites */
 } lq_energy_terms;
 

@@ -39,7 +39,8 @@ class _Problem(C.Structure):
                 ("A", C.c_double), ("B", C.c_double), ("C", C.c_double),
                 ("L1", C.c_double), ("L2", C.c_double), ("L3", C.c_double),
                 ("type", C.c_void_p), ("n_pairs", C.c_int64), ("pair_site", C.c_void_p),
-                ("pair_W", C.c_void_p), ("pair_Q0", C.c_void_p)]
+                ("pair_W", C.c_void_p), ("pair_Q0", C.c_void_p), ("pair_kind", C.c_void_p),
+                ("pair_nu", C.c_void_p), ("S0", C.c_double), ("hfield", C.c_double * 9)]
 
 
 class FireParams(C.Structure):
@@ -125,7 +126,9 @@ class Problem:
 
     def __init__(self, shape, periodic=(True, True, True), A=-0.172, B=-2.12, C_=1.73,
                  L1=2.32, L2=0.0, L3=0.0, objects=(), site_records=(), object_sites=(),
-                 types=None, pairs=None):
+                 types=None, pairs=None, fields=()):
+        """fields: (h, chi) pairs giving f_ext = -(1/3) sum chi (h.Q.h), sec. II.C
+        (chi = mu0 dchi or eps0 deps in units of |A|, h the field vector)."""
         self.shape = tuple(int(s) for s in shape)
         self.periodic = tuple(bool(p) for p in periodic)
         for k in range(3):
@@ -134,21 +137,31 @@ class Problem:
         self.A, self.B, self.C, self.L1, self.L2, self.L3 = A, B, C_, L1, L2, L3
         self.S0 = S0(A, B, C_)
         if types is None:
-            types, ps, pw, pq = rasterize(self.shape, self.periodic, list(objects), self.S0,
-                                          site_records, object_sites)
+            types, ps, pw, pq, pk, pn = rasterize(self.shape, self.periodic, list(objects), self.S0,
+                                                  site_records, object_sites, full=True)
         else:
             ps, pw, pq = pairs
+            pk = np.zeros(len(ps), np.uint8)
+            pn = np.zeros((len(ps), 3))
         self.types = np.ascontiguousarray(types, dtype=np.uint8)
         self.pair_site = np.ascontiguousarray(ps, dtype=np.int64)
         self.pair_W = np.ascontiguousarray(pw, dtype=np.float64)
         self.pair_Q0 = np.ascontiguousarray(pq, dtype=np.float64).reshape(-1, 5)
+        self.pair_kind = np.ascontiguousarray(pk, dtype=np.uint8)
+        self.pair_nu = np.ascontiguousarray(pn, dtype=np.float64).reshape(-1, 3)
+        self.hfield = np.zeros((3, 3))
+        for h, chi in fields:
+            h = np.asarray(h, dtype=np.float64)
+            self.hfield += chi / 3.0 * np.outer(h, h)
         nx, ny, nz = self.shape
         self.N = nx * ny * nz
         self._s = _Problem((C.c_int64 * 3)(nx, ny, nz),
                            (C.c_int32 * 3)(*[int(p) for p in self.periodic]),
                            A, B, C_, L1, L2, L3, self.types.ctypes.data, len(self.pair_site),
                            self.pair_site.ctypes.data, self.pair_W.ctypes.data,
-                           self.pair_Q0.ctypes.data)
+                           self.pair_Q0.ctypes.data, self.pair_kind.ctypes.data,
+                           self.pair_nu.ctypes.data, self.S0,
+                           (C.c_double * 9)(*self.hfield.reshape(-1).tolist()))
 
     @property
     def field_shape(self):
@@ -174,7 +187,7 @@ class Problem:
 
     def energy(self, q, terms=False):
         q = self._chk(q)
-        t = np.zeros(3)
+        t = np.zeros(4)
         e = lib().ora_energy(C.byref(self._s), _dp(q), _dp(t))
         return (e, t) if terms else e
 

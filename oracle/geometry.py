@@ -18,7 +18,12 @@ What it encodes (paper sec. III.B, site typing; sec. II.D, anchoring):
   * preferred tensor Q0 = 3/2 S0 (n0 n0 - I/3) (sec. II.D);
   * the strength used in W tr((Q - Q0)^2) is W for the Nobili-Durand law and
     W / (9 S0^2) for a Rapini-Papoular strength (sec. II.D, the relation
-    W_RP = 9 S0^2 W_ND).
+    W_RP = 9 S0^2 W_ND);
+  * degenerate planar anchoring uses the Fournier-Galatola form
+    W |Qt - P Qt P|^2 with the surface normal nu (sec. II.D): law "fg" takes
+    W as the Fournier-Galatola strength, and a negative Rapini-Papoular
+    strength (which the paper assigns to degenerate planar anchoring) enters
+    as |W| / (9 S0^2).
 """
 from __future__ import annotations
 
@@ -65,18 +70,31 @@ def q_from_director(n, S):
                      h * (ny * ny - 1.0 / 3.0), h * ny * nz])
 
 
+KIND_ND, KIND_FG = 0, 1
+
+
 def _strength(obj_or_rec, S0):
+    """(kind, strength) of an object or record."""
     law = obj_or_rec.get("law", "nd")
     W = float(obj_or_rec["W"])
     if law == "nd":
-        return W
+        if W < 0:
+            raise ValueError("negative Nobili-Durand strength")
+        return KIND_ND, W
     if law == "rp":
-        return W / (9.0 * S0 * S0)
+        if W < 0:
+            return KIND_FG, -W / (9.0 * S0 * S0)
+        return KIND_ND, W / (9.0 * S0 * S0)
+    if law == "fg":
+        if W < 0:
+            raise ValueError("negative Fournier-Galatola strength")
+        return KIND_FG, W
     raise ValueError(f"unknown anchoring law {law!r}")
 
 
-def rasterize(shape, periodic, objects, S0, site_records=(), object_sites=()):
-    """Returns (types uint8[N], pair_site int64[P], pair_W float64[P], pair_Q0 float64[P,5]).
+def rasterize(shape, periodic, objects, S0, site_records=(), object_sites=(), full=False):
+    """Returns (types uint8[N], pair_site int64[P], pair_W float64[P], pair_Q0 float64[P,5]),
+    and with full=True also pair_kind uint8[P] and pair_nu float64[P,3].
 
     shape = (nx, ny, nz); sites are numbered x + nx*(y + ny*z).
     objects: dicts with kind wall / sphere / patterned_wall (see module doc).
@@ -96,7 +114,7 @@ def rasterize(shape, periodic, objects, S0, site_records=(), object_sites=()):
         obj.reshape(-1)[np.asarray(object_sites, dtype=np.int64)] = True
     sim = ~obj
 
-    sites_l, W_l, Q0_l = [], [], []
+    sites_l, W_l, Q0_l, K_l, nu_l = [], [], [], [], []
     for o, m in zip(objects, inside):
         touch = np.zeros_like(m)
         for k in range(3):
@@ -130,30 +148,43 @@ def rasterize(shape, periodic, objects, S0, site_records=(), object_sites=()):
                 v = np.asarray(d, dtype=np.float64)
                 v = v / np.sqrt((v * v).sum())
                 n0 = np.repeat(v[:, None], flat.size, axis=1)
+        kind, Ws = _strength(o, S0)
         sites_l.append(flat.astype(np.int64))
-        W_l.append(np.full(flat.size, _strength(o, S0)))
+        W_l.append(np.full(flat.size, Ws))
         Q0_l.append(q_from_director(n0, S0).T)
+        K_l.append(np.full(flat.size, kind, dtype=np.uint8))
+        nu_l.append(np.ascontiguousarray(nu.T))
 
     for r in site_records:
         s = int(r["site"])
         if not sim.reshape(-1)[s]:
             raise ValueError(f"anchoring record at non-simulated site {s}")
-        v = np.asarray(r["n0"], dtype=np.float64)
+        kind, Ws = _strength(r, S0)
+        key = "nu" if kind == KIND_FG else "n0"
+        v = np.asarray(r[key], dtype=np.float64)
         v = v / np.sqrt((v * v).sum())
         sites_l.append(np.array([s], dtype=np.int64))
-        W_l.append(np.array([_strength(r, S0)]))
+        W_l.append(np.array([Ws]))
         Q0_l.append(q_from_director(v[:, None], S0).T)
+        K_l.append(np.array([kind], dtype=np.uint8))
+        nu_l.append(v[None, :])
 
     if sites_l:
         ps = np.concatenate(sites_l)
         pw = np.concatenate(W_l)
         pq = np.ascontiguousarray(np.concatenate(Q0_l, axis=0))
+        pk = np.concatenate(K_l)
+        pn = np.ascontiguousarray(np.concatenate(nu_l, axis=0))
     else:
         ps = np.zeros(0, np.int64)
         pw = np.zeros(0)
         pq = np.zeros((0, 5))
+        pk = np.zeros(0, np.uint8)
+        pn = np.zeros((0, 3))
     types = np.where(obj.reshape(-1), 2, 0).astype(np.uint8)
     types[ps] = 1
+    if full:
+        return types, ps, pw, pq, pk, pn
     return types, ps, pw, pq
 
 

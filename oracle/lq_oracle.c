@@ -17,7 +17,9 @@
  *     the one-sided differences of Eq. (onesidedderivatives) and averaged over
  *     every allowed forward/backward choice per axis (sec. III.B, text after
  *     Eq. onesidedderivatives);
- *   - Nobili-Durand anchoring W tr((Q - Q0)^2) on boundary pairs (sec. II.D);
+ *   - Nobili-Durand anchoring W tr((Q - Q0)^2) and Fournier-Galatola
+ *     degenerate planar anchoring on boundary pairs (sec. II.D);
+ *   - external fields, linear in Q (sec. II.C);
  *   - forces F = -dE/dq by explicit differentiation of the discrete energy
  *     (sec. III.B, the paragraph on explicit differentiation);
  *   - FIRE, Algorithm 1 (after Bitzek et al., PRL 97, 170201 (2006)).
@@ -40,8 +42,12 @@ typedef struct {
     const uint8_t *type;   /* per site: 0 bulk, 1 boundary, 2 object */
     int64_t n_pairs;       /* anchoring (site, surface) pairs */
     const int64_t *pair_site;
-    const double *pair_W;  /* Nobili-Durand strength used for the pair */
-    const double *pair_Q0; /* [n_pairs][5] preferred tensor, q components */
+    const double *pair_W;  /* strength used for the pair */
+    const double *pair_Q0; /* [n_pairs][5] preferred tensor, q components (Nobili-Durand) */
+    const uint8_t *pair_kind; /* 0: Nobili-Durand, 1: Fournier-Galatola (may be NULL: all 0) */
+    const double *pair_nu;    /* [n_pairs][3] surface normal (Fournier-Galatola) */
+    double S0;                /* bulk order used by Fournier-Galatola, sec. II.D */
+    double hfield[9];         /* external-field coupling: f_ext = -sum_ij Q_ij h_ij, sec. II.C */
 } ora_problem;
 
 #ifdef _OPENMP
@@ -281,9 +287,81 @@ static void add_dist_grad_from(const ora_problem *p, const double *q, int64_t x,
             }
 }
 
-/* ---- energy: E = sum over simulated sites of (f_bulk + averaged f_dist)
- *      + sum over boundary pairs of W tr((Q - Q0)^2).
- *      terms[0] bulk, terms[1] distortion, terms[2] anchoring.
+/* ---- anchoring of one (site, surface) pair, sec. II.D ----
+ * Nobili-Durand:      W tr((Q - Q0)^2)
+ * Fournier-Galatola:  W |Qt - P Qt P|^2, Qt = Q + S0/2 I, P = I - nu nu
+ * (the projector of Eq. planarDegenerate read as P_ik Qt_kl P_lj). */
+static void fg_D(const ora_problem *p, int64_t i, const double Q[3][3], double D[3][3], double P[3][3])
+{
+    const double *nu = &p->pair_nu[3 * i];
+    double Qt[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            P[a][b] = (a == b ? 1.0 : 0.0) - nu[a] * nu[b];
+            Qt[a][b] = Q[a][b] + (a == b ? 0.5 * p->S0 : 0.0);
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) s += P[a][k] * Qt[k][l] * P[l][b];
+            D[a][b] = Qt[a][b] - s;
+        }
+}
+
+static int pair_is_fg(const ora_problem *p, int64_t i) { return p->pair_kind && p->pair_kind[i] == 1; }
+
+static double pair_energy(const ora_problem *p, int64_t i, const double Q[3][3])
+{
+    double t = 0.0;
+    if (pair_is_fg(p, i)) {
+        double D[3][3], P[3][3];
+        fg_D(p, i, Q, D, P);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) t += D[a][b] * D[a][b];
+    } else {
+        double Q0[3][3];
+        q_to_Q(&p->pair_Q0[5 * i], Q0);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) t += (Q[a][b] - Q0[a][b]) * (Q[a][b] - Q0[a][b]);
+    }
+    return p->pair_W[i] * t;
+}
+
+/* adds d(pair energy)/dQ: 2 W (Q - Q0), or 2 W (D - P D P) for Fournier-Galatola */
+static void add_pair_grad(const ora_problem *p, int64_t i, const double Q[3][3], double G[3][3])
+{
+    if (pair_is_fg(p, i)) {
+        double D[3][3], P[3][3];
+        fg_D(p, i, Q, D, P);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l) s += P[a][k] * D[k][l] * P[l][b];
+                G[a][b] += 2.0 * p->pair_W[i] * (D[a][b] - s);
+            }
+    } else {
+        double Q0[3][3];
+        q_to_Q(&p->pair_Q0[5 * i], Q0);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) G[a][b] += 2.0 * p->pair_W[i] * (Q[a][b] - Q0[a][b]);
+    }
+}
+
+/* external-field density -sum_ij Q_ij h_ij (linear in Q), sec. II.C */
+static double f_ext(const ora_problem *p, const double Q[3][3])
+{
+    double t = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) t -= Q[a][b] * p->hfield[3 * a + b];
+    return t;
+}
+
+/* ---- energy: E = sum over simulated sites of (f_bulk + averaged f_dist
+ *      + f_ext) + sum over boundary pairs of the anchoring term.
+ *      terms[0] bulk, terms[1] distortion, terms[2] anchoring, terms[3]
+ *      external field.
  *      Per-plane partial sums are added in plane order, so the result does
  *      not depend on the number of threads. ---- */
 double ora_energy(const ora_problem *p, const double *q, double *terms)
@@ -291,9 +369,10 @@ double ora_energy(const ora_problem *p, const double *q, double *terms)
     int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
     double *pb = (double *)calloc((size_t)nz, sizeof(double));
     double *pd = (double *)calloc((size_t)nz, sizeof(double));
+    double *pe = (double *)calloc((size_t)nz, sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int64_t z = 0; z < nz; ++z) {
-        double sb = 0.0, sd = 0.0;
+        double sb = 0.0, sd = 0.0, se = 0.0;
         for (int64_t y = 0; y < ny; ++y)
             for (int64_t x = 0; x < nx; ++x) {
                 int64_t s = x + nx * (y + ny * z);
@@ -301,33 +380,34 @@ double ora_energy(const ora_problem *p, const double *q, double *terms)
                 double Q[3][3];
                 load_Q(p, q, s, Q);
                 sb += f_bulk(p, Q);
+                se += f_ext(p, Q);
                 sd += e_dist_site(p, q, s);
             }
         pb[z] = sb;
         pd[z] = sd;
+        pe[z] = se;
     }
-    double eb = 0.0, ed = 0.0, ea = 0.0;
+    double eb = 0.0, ed = 0.0, ea = 0.0, ee = 0.0;
     for (int64_t z = 0; z < nz; ++z) {
         eb += pb[z];
         ed += pd[z];
+        ee += pe[z];
     }
     free(pb);
     free(pd);
+    free(pe);
     for (int64_t i = 0; i < p->n_pairs; ++i) {
-        double Q[3][3], Q0[3][3];
+        double Q[3][3];
         load_Q(p, q, p->pair_site[i], Q);
-        q_to_Q(&p->pair_Q0[5 * i], Q0);
-        double t = 0.0;
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) t += (Q[a][b] - Q0[a][b]) * (Q[a][b] - Q0[a][b]);
-        ea += p->pair_W[i] * t;
+        ea += pair_energy(p, i, Q);
     }
     if (terms) {
         terms[0] = eb;
         terms[1] = ed;
         terms[2] = ea;
+        terms[3] = ee;
     }
-    return eb + ed + ea;
+    return eb + ed + ea + ee;
 }
 
 /* ---- forces F = -dE/dq.  Each site y gathers the derivative of every
@@ -350,6 +430,7 @@ void ora_forces(const ora_problem *p, const double *q, double *F)
                     double Q[3][3];
                     load_Q(p, q, y, Q);
                     grad_bulk(p, Q, G);
+                    for (int a = 0; a < 9; ++a) G[a / 3][a % 3] -= p->hfield[a];
                     add_dist_grad_from(p, q, y, y, G);
                     int64_t c[3] = {xx, yy, z};
                     for (int k = 0; k < 3; ++k)
@@ -361,14 +442,12 @@ void ora_forces(const ora_problem *p, const double *q, double *F)
                 }
                 for (int a = 0; a < 5; ++a) F[a * N + y] = -g[a];
             }
-    /* anchoring, serial over pairs: d/dQ of W tr((Q-Q0)^2) = 2 W (Q - Q0) */
+    /* anchoring, serial over pairs */
     for (int64_t i = 0; i < p->n_pairs; ++i) {
         int64_t s = p->pair_site[i];
-        double Q[3][3], Q0[3][3], Ga[3][3], g[5];
+        double Q[3][3], Ga[3][3] = {{0}}, g[5];
         load_Q(p, q, s, Q);
-        q_to_Q(&p->pair_Q0[5 * i], Q0);
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) Ga[a][b] = 2.0 * p->pair_W[i] * (Q[a][b] - Q0[a][b]);
+        add_pair_grad(p, i, Q, Ga);
         grad_Q_to_q(Ga, g);
         for (int a = 0; a < 5; ++a) F[a * N + s] -= g[a];
     }
@@ -516,7 +595,7 @@ double ora_site_energy(const ora_problem *p, const double *q, int64_t s)
     if (!simulated(p, s)) return 0.0;
     double Q[3][3];
     load_Q(p, q, s, Q);
-    return f_bulk(p, Q) + e_dist_site(p, q, s);
+    return f_bulk(p, Q) + f_ext(p, Q) + e_dist_site(p, q, s);
 }
 
 /* ---- force at a list of sites only (for sampled checks on lattices too
@@ -535,19 +614,15 @@ void ora_forces_at(const ora_problem *p, const double *q, int64_t n_sites, const
             coords(p, y, c);
             load_Q(p, q, y, Q);
             grad_bulk(p, Q, G);
+            for (int a = 0; a < 9; ++a) G[a / 3][a % 3] -= p->hfield[a];
             add_dist_grad_from(p, q, y, y, G);
             for (int k = 0; k < 3; ++k)
                 for (int s = -1; s <= 1; s += 2) {
                     int64_t x = neighbour(p, c, k, s);
                     if (simulated(p, x)) add_dist_grad_from(p, q, x, y, G);
                 }
-            for (int64_t j = 0; j < p->n_pairs; ++j) {
-                if (p->pair_site[j] != y) continue;
-                double Q0[3][3];
-                q_to_Q(&p->pair_Q0[5 * j], Q0);
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) G[a][b] += 2.0 * p->pair_W[j] * (Q[a][b] - Q0[a][b]);
-            }
+            for (int64_t j = 0; j < p->n_pairs; ++j)
+                if (p->pair_site[j] == y) add_pair_grad(p, j, Q, G);
             grad_Q_to_q(G, g);
         }
         for (int a = 0; a < 5; ++a) out[5 * i + a] = -g[a];

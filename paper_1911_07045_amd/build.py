@@ -9,11 +9,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INC = os.path.join(ROOT, "include")
-BUILD = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "liblqfire.so")
+BUILD = os.environ.get("LQ_BUILD_DIR", os.path.join(HERE, "_build"))
+LIB = os.environ.get("LQ_LIB_OUT", os.path.join(HERE, "liblqfire.so"))
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INC, "-I", CSRC]
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INC, "-I", CSRC] + os.environ.get("LQ_EXTRA_FLAGS", "").split()
 # packed FP32 instructions stay off for all device code
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-ffp-contract=on"]

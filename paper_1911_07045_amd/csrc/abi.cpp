@@ -28,7 +28,7 @@ struct lq_lattice {
     // device geometry
     uint8_t* d_mask = nullptr;
     uint8_t* d_tile = nullptr;
-    int32_t* d_anch_site = nullptr;
+    int32_t* d_anch_index = nullptr;
     double* d_anch_data = nullptr;
     int n_anch = 0;
     // energy scratch
@@ -179,10 +179,10 @@ static void tile_flags(const lq_params& p, const std::vector<uint8_t>& mask, int
 static void free_geometry(lq_lattice* lat) {
     if (lat->d_mask) (void)hipFree(lat->d_mask);
     if (lat->d_tile) (void)hipFree(lat->d_tile);
-    if (lat->d_anch_site) (void)hipFree(lat->d_anch_site);
+    if (lat->d_anch_index) (void)hipFree(lat->d_anch_index);
     if (lat->d_anch_data) (void)hipFree(lat->d_anch_data);
     lat->d_mask = lat->d_tile = nullptr;
-    lat->d_anch_site = nullptr;
+    lat->d_anch_index = nullptr;
     lat->d_anch_data = nullptr;
 }
 
@@ -209,9 +209,11 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     HIPCHK(lat, hipMemcpy(lat->d_tile, tiles.data(), tiles.size(), hipMemcpyHostToDevice));
     lat->n_anch = (int)g.anch_site.size();
     if (lat->n_anch > 0) {
-        std::vector<int32_t> s32(g.anch_site.begin(), g.anch_site.end());
-        HIPCHK(lat, hipMalloc(&lat->d_anch_site, s32.size() * sizeof(int32_t)));
-        HIPCHK(lat, hipMemcpy(lat->d_anch_site, s32.data(), s32.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        // dense per-site row index (1-based; 0 = no anchoring)
+        std::vector<int32_t> idx((size_t)lat->N, 0);
+        for (size_t i = 0; i < g.anch_site.size(); ++i) idx[(size_t)g.anch_site[i]] = (int32_t)i + 1;
+        HIPCHK(lat, hipMalloc(&lat->d_anch_index, idx.size() * sizeof(int32_t)));
+        HIPCHK(lat, hipMemcpy(lat->d_anch_index, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(lat, hipMalloc(&lat->d_anch_data, g.anch_data.size() * sizeof(double)));
         HIPCHK(lat, hipMemcpy(lat->d_anch_data, g.anch_data.data(), g.anch_data.size() * sizeof(double),
                               hipMemcpyHostToDevice));
@@ -219,7 +221,7 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     d.mask = lat->d_mask;
     d.tile_bulk = lat->d_tile;
     d.n_anch = lat->n_anch;
-    d.anch_site = lat->d_anch_site;
+    d.anch_index = lat->d_anch_index;
     d.anch_data = lat->d_anch_data;
     lat->n_sim = g.n_sim;
     lat->bound = false;
@@ -303,7 +305,7 @@ int lq_rasterize(const lq_params* p, const lq_object* objs, int32_t n_objs, cons
     const int64_t n = std::min<int64_t>(cap, (int64_t)g.anch_site.size());
     for (int64_t i = 0; i < n; ++i) {
         anch_site[i] = g.anch_site[i];
-        std::memcpy(anch_data + 7 * i, &g.anch_data[7 * i], 7 * sizeof(double));
+        std::memcpy(anch_data + ANCH_STRIDE * i, &g.anch_data[ANCH_STRIDE * i], ANCH_STRIDE * sizeof(double));
     }
     return LQ_OK;
 }
@@ -316,6 +318,28 @@ int lq_set_boundaries(lq_lattice* lat, const lq_object* objs, int32_t n_objs, co
     int rc = rasterize(lat->p, lat->S0, objs, n_objs, recs, n_recs, object_sites, n_object_sites, g, err);
     if (rc != LQ_OK) return fail(lat, rc, err);
     return upload_geometry(lat, g);
+}
+
+int lq_set_field(lq_lattice* lat, const double* h, const double* chi, int32_t n_fields) {
+    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
+    if (n_fields < 0 || (n_fields > 0 && (!h || !chi))) return fail(lat, LQ_EINVAL, "bad field arrays");
+    // hf = sum chi/3 h h^T; the force on q is +P^T hf
+    double hf[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int32_t f = 0; f < n_fields; ++f) {
+        const double* v = h + 3 * (int64_t)f;
+        if (!std::isfinite(chi[f]) || !std::isfinite(v[0]) || !std::isfinite(v[1]) || !std::isfinite(v[2]))
+            return fail(lat, LQ_EINVAL, "field is not finite");
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) hf[a][b] += chi[f] / 3.0 * v[a] * v[b];
+    }
+    double* e = lat->dev.ext;
+    e[0] = hf[0][0] - hf[2][2];
+    e[1] = hf[0][1] + hf[1][0];
+    e[2] = hf[0][2] + hf[2][0];
+    e[3] = hf[1][1] - hf[2][2];
+    e[4] = hf[1][2] + hf[2][1];
+    lat->bound = false;
+    return LQ_OK;
 }
 
 int lq_set_uniaxial(lq_lattice* lat, const double* directors, double S, void* q) {
@@ -356,7 +380,8 @@ int lq_energy(lq_lattice* lat, const void* q, lq_energy_terms* out) {
     out->bulk = lat->h_eout->bulk;
     out->elastic = lat->h_eout->elastic;
     out->anchoring = lat->h_eout->anch;
-    out->total = out->bulk + out->elastic + out->anchoring;
+    out->external = lat->h_eout->ext;
+    out->total = out->bulk + out->elastic + out->anchoring + out->external;
     out->n_sim = lat->n_sim;
     return LQ_OK;
 }

@@ -1,13 +1,17 @@
 // Host rasterizer of liblqfire: objects and per-site records -> site types,
-// neighbour masks and per-site anchoring sums.
+// neighbour masks and per-site anchoring forms.
 //
 // Site typing follows sec. III.B (bulk, boundary, inside an object; only
-// bulk and boundary sites are simulated).  Anchoring follows sec. II.D: the
-// Nobili-Durand term W tr((Q - Q0)^2) with Q0 = 3/2 S0 (n0 n0 - I/3); a
-// Rapini-Papoular strength enters as W / (9 S0^2).  Because every term is
-// quadratic in Q, the terms of one site are stored as their sums
-// {sum W, sum W Q0, sum W tr(Q0^2)}, from which the kernels rebuild both the
-// energy and the force.
+// bulk and boundary sites are simulated).  Anchoring follows sec. II.D:
+//   - Nobili-Durand W tr((Q - Q0)^2), Q0 = 3/2 S0 (n0 n0 - I/3); a
+//     Rapini-Papoular strength W >= 0 enters as W / (9 S0^2);
+//   - Fournier-Galatola W |Qt - P Qt P|^2, Qt = Q + S0/2 I, P = I - nu nu
+//     (degenerate planar); a Rapini-Papoular strength W < 0 enters as
+//     |W| / (9 S0^2).
+// Both are quadratic in the five components q, so the terms of one site are
+// summed into one form f = 1/2 q^T K q + b^T q + c, stored as the upper
+// triangle of K (15 values), b (5) and c (1); the kernels take the force
+// -(K q + b) and the energy from it.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -52,10 +56,69 @@ void q_of(const double nv[3], double S, double out[5]) {
     out[4] = h * nv[1] * nv[2];
 }
 
-// tr(Q^2) from q components, full tensor with Qzz = -Qxx - Qyy
-double tr2_of(const double q[5]) {
-    double zz = -q[0] - q[3];
-    return q[0] * q[0] + q[3] * q[3] + zz * zz + 2.0 * (q[1] * q[1] + q[2] * q[2] + q[4] * q[4]);
+// The symmetric traceless tensor of the unit q component a (Qzz = -Qxx - Qyy).
+void basis(int a, double E[3][3]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) E[i][j] = 0.0;
+    switch (a) {
+        case 0: E[0][0] = 1.0; E[2][2] = -1.0; break;
+        case 1: E[0][1] = E[1][0] = 1.0; break;
+        case 2: E[0][2] = E[2][0] = 1.0; break;
+        case 3: E[1][1] = 1.0; E[2][2] = -1.0; break;
+        default: E[1][2] = E[2][1] = 1.0; break;
+    }
+}
+
+double frob(const double X[3][3], const double Y[3][3]) {
+    double s = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) s += X[i][j] * Y[i][j];
+    return s;
+}
+
+// position of K[a][b] (a <= b) in the stored upper triangle
+int tri(int a, int b) { return a * 5 - a * (a - 1) / 2 + (b - a); }
+
+// d += form of W tr((Q - Q0)^2) = W (q - q0)^T M (q - q0), M_ab = E_a : E_b
+void add_nd(double* d, double W, const double q0[5]) {
+    double E[5][3][3];
+    for (int a = 0; a < 5; ++a) basis(a, E[a]);
+    double M[5][5];
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b) M[a][b] = frob(E[a], E[b]);
+    for (int a = 0; a < 5; ++a) {
+        for (int b = a; b < 5; ++b) d[tri(a, b)] += 2.0 * W * M[a][b];
+        double Mq0 = 0.0;
+        for (int b = 0; b < 5; ++b) Mq0 += M[a][b] * q0[b];
+        d[15 + a] += -2.0 * W * Mq0;
+        d[20] += W * q0[a] * Mq0;
+    }
+}
+
+// d += form of W |D|^2, D = L(q) + D0, L_a = E_a - P E_a P, D0 = S0/2 nu nu
+void add_fg(double* d, double W, const double nu[3], double S0) {
+    double P[3][3], D0[3][3], Lb[5][3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            P[i][j] = (i == j ? 1.0 : 0.0) - nu[i] * nu[j];
+            D0[i][j] = 0.5 * S0 * nu[i] * nu[j];
+        }
+    for (int a = 0; a < 5; ++a) {
+        double E[3][3];
+        basis(a, E);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l) s += P[i][k] * E[k][l] * P[l][j];
+                Lb[a][i][j] = E[i][j] - s;
+            }
+    }
+    for (int a = 0; a < 5; ++a) {
+        for (int b = a; b < 5; ++b) d[tri(a, b)] += 2.0 * W * frob(Lb[a], Lb[b]);
+        d[15 + a] += 2.0 * W * frob(Lb[a], D0);
+    }
+    d[20] += W * frob(D0, D0);
 }
 
 bool normalize(const double in[3], double out[3]) {
@@ -67,21 +130,27 @@ bool normalize(const double in[3], double out[3]) {
     return true;
 }
 
-bool strength(int32_t law, double W, double S0, double* out, std::string& err) {
+// kind of term (false: Nobili-Durand, true: Fournier-Galatola) and its strength
+bool strength(int32_t law, double W, double S0, bool* fg, double* out, std::string& err) {
     if (!std::isfinite(W)) {
         err = "anchoring strength is not finite";
         return false;
     }
-    if (W < 0.0) {
-        err = "negative anchoring strength (degenerate planar anchoring is not supported)";
-        return false;
-    }
+    *fg = false;
     if (law == LQ_LAW_ND) {
         *out = W;
     } else if (law == LQ_LAW_RP) {
-        *out = W / (9.0 * S0 * S0);
+        *fg = W < 0.0;
+        *out = std::fabs(W) / (9.0 * S0 * S0);
+    } else if (law == LQ_LAW_FG) {
+        *fg = true;
+        *out = W;
     } else {
         err = "unknown anchoring law";
+        return false;
+    }
+    if (*out < 0.0) {
+        err = "negative Nobili-Durand or Fournier-Galatola strength";
         return false;
     }
     return true;
@@ -138,6 +207,22 @@ void object_interior(const lq_object& o, const Lat& L, std::vector<int64_t>& out
         }
 }
 
+// surface normal of object o seen from boundary site (x, y, z)
+void surface_normal(const lq_object& o, const Lat& L, int64_t x, int64_t y, int64_t z, double nu[3]) {
+    nu[0] = nu[1] = nu[2] = 0.0;
+    if (o.kind == LQ_OBJ_WALL || o.kind == LQ_OBJ_PATTERNED_WALL) {
+        nu[o.axis] = 1.0;
+        return;
+    }
+    double d[3] = {min_image((double)x - o.center[0], L.n[0], L.per[0]),
+                   min_image((double)y - o.center[1], L.n[1], L.per[1]),
+                   min_image((double)z - o.center[2], L.n[2], L.per[2])};
+    double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    nu[0] = d[0] / r;
+    nu[1] = d[1] / r;
+    nu[2] = d[2] / r;
+}
+
 // preferred director of object o at boundary site (x, y, z)
 void preferred_director(const lq_object& o, const Lat& L, int64_t x, int64_t y, int64_t z,
                         double n0[3]) {
@@ -164,18 +249,8 @@ void preferred_director(const lq_object& o, const Lat& L, int64_t x, int64_t y, 
         n0[w] = bw / r;
         return;
     }
-    double nu[3] = {0.0, 0.0, 0.0};
-    if (o.kind == LQ_OBJ_WALL) {
-        nu[o.axis] = 1.0;
-    } else {
-        double d[3] = {min_image((double)x - o.center[0], L.n[0], L.per[0]),
-                       min_image((double)y - o.center[1], L.n[1], L.per[1]),
-                       min_image((double)z - o.center[2], L.n[2], L.per[2])};
-        double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        nu[0] = d[0] / r;
-        nu[1] = d[1] / r;
-        nu[2] = d[2] / r;
-    }
+    double nu[3];
+    surface_normal(o, L, x, y, z, nu);
     if (o.dir_mode == LQ_DIR_FIXED) {
         normalize(o.dir, n0);
     } else {
@@ -247,10 +322,6 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
     bool anchoring = n_recs > 0;
     for (int32_t i = 0; i < n_objs; ++i) {
         if (!check_object(objs[i], L, err)) return LQ_EINVAL;
-        if (objs[i].law == LQ_LAW_RP && objs[i].W < 0.0) {
-            err = "Rapini-Papoular W < 0 (degenerate planar) needs the Fournier-Galatola form";
-            return LQ_EUNSUPPORTED;
-        }
         anchoring = true;
     }
     if (anchoring && !(std::isfinite(S0) && S0 > 0.0)) {
@@ -271,28 +342,24 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
         }
         g.type[s] = 2;
     }
-    // per-site anchoring sums, indexed by site through a sparse map
+    // per-site anchoring forms, indexed by site through a sparse map
     std::vector<int64_t> slot((size_t)N, -1);
     std::vector<int64_t> sites;
     std::vector<double> data;
-    auto add_term = [&](int64_t s, double W, const double n0[3]) {
+    auto row = [&](int64_t s) -> double* {
         if (slot[s] < 0) {
             slot[s] = (int64_t)sites.size();
             sites.push_back(s);
-            data.insert(data.end(), 7, 0.0);
+            data.insert(data.end(), ANCH_STRIDE, 0.0);
         }
-        double q0[5];
-        q_of(n0, S0, q0);
-        double* d = &data[7 * slot[s]];
-        d[0] += W;
-        for (int a = 0; a < 5; ++a) d[1 + a] += W * q0[a];
-        d[6] += W * tr2_of(q0);
+        return &data[ANCH_STRIDE * slot[s]];
     };
     std::vector<int32_t> last((size_t)N, -1);
     for (int32_t i = 0; i < n_objs; ++i) {
         const lq_object& o = objs[i];
         double W;
-        if (!strength(o.law, o.W, S0, &W, err)) return LQ_EINVAL;
+        bool fg;
+        if (!strength(o.law, o.W, S0, &fg, &W, err)) return LQ_EINVAL;
         for (int64_t s : interior[i]) {
             int64_t c[3] = {s % L.n[0], (s / L.n[0]) % L.n[1], s / (L.n[0] * L.n[1])};
             for (int k = 0; k < 3; ++k)
@@ -301,9 +368,16 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
                     if (t < 0 || g.type[t] == 2 || last[t] == i) continue;
                     last[t] = i;
                     int64_t tc[3] = {t % L.n[0], (t / L.n[0]) % L.n[1], t / (L.n[0] * L.n[1])};
-                    double n0[3];
-                    preferred_director(o, L, tc[0], tc[1], tc[2], n0);
-                    add_term(t, W, n0);
+                    if (fg) {
+                        double nu[3];
+                        surface_normal(o, L, tc[0], tc[1], tc[2], nu);
+                        add_fg(row(t), W, nu, S0);
+                    } else {
+                        double n0[3], q0[5];
+                        preferred_director(o, L, tc[0], tc[1], tc[2], n0);
+                        q_of(n0, S0, q0);
+                        add_nd(row(t), W, q0);
+                    }
                 }
         }
     }
@@ -314,12 +388,19 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
             return LQ_EINVAL;
         }
         double W, n0[3];
-        if (!strength(r.law, r.W, S0, &W, err)) return r.law == LQ_LAW_RP && r.W < 0 ? LQ_EUNSUPPORTED : LQ_EINVAL;
+        bool fg;
+        if (!strength(r.law, r.W, S0, &fg, &W, err)) return LQ_EINVAL;
         if (!normalize(r.n0, n0)) {
             err = "anchoring record director is zero or not finite";
             return LQ_EINVAL;
         }
-        add_term(r.site, W, n0);
+        if (fg) {
+            add_fg(row(r.site), W, n0, S0);
+        } else {
+            double q0[5];
+            q_of(n0, S0, q0);
+            add_nd(row(r.site), W, q0);
+        }
     }
     // sort the anchored sites
     std::vector<int64_t> order(sites.size());
@@ -329,7 +410,7 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
     g.anch_data.resize(data.size());
     for (size_t i = 0; i < order.size(); ++i) {
         g.anch_site[i] = sites[order[i]];
-        std::memcpy(&g.anch_data[7 * i], &data[7 * order[i]], 7 * sizeof(double));
+        std::memcpy(&g.anch_data[ANCH_STRIDE * i], &data[ANCH_STRIDE * order[i]], ANCH_STRIDE * sizeof(double));
         g.type[sites[order[i]]] = 1;
     }
     // neighbour masks

@@ -256,6 +256,9 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK>& P, uint3
     P.load5(0, 0, 0, q0);
     T g[5];
     bulk_grad(q0, A, B, C, g);
+    // external fields: a constant force per simulated site
+#pragma unroll
+    for (int c = 0; c < 5; ++c) g[c] -= T(L.ext[c]);
     if (BULK && !L23) {
         // every bond has weight 1: the L1 term is -L1 M (sum of neighbours - 6 q)
 #pragma unroll
@@ -327,27 +330,28 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK>& P, uint3
         }
     }
     if (!BULK && (m0 & M_ANCH)) {
-        // binary search of the site in the sorted anchored list
-        int lo = 0, hi = L.n_anch - 1, at = -1;
-        while (lo <= hi) {
-            int mid = (lo + hi) >> 1;
-            int sv = L.anch_site[mid];
-            if (sv == site) { at = mid; break; }
-            if (sv < site) lo = mid + 1; else hi = mid - 1;
-        }
+        // row of the site's anchoring form; the range-checked load gives 0
+        // (no anchoring) for a site index outside the lattice
+        const __amdgpu_buffer_rsrc_t ri = field_rsrc(L.anch_index, (uint32_t)L.N * 4u);
+        const int at = (int)__builtin_amdgcn_raw_buffer_load_b32(
+                           ri, (int)(site >= 0 ? (uint32_t)site * 4u : 0xFFFFFFFFu), 0, 0) - 1;
         if (at >= 0) {
-            const double* d = L.anch_data + 7 * (int64_t)at;
-            T W = T(d[0]);
-            T qw[5] = {T(d[1]), T(d[2]), T(d[3]), T(d[4]), T(d[5])};
-            // d/dq of sum W tr((Q - Q0)^2) = P^T 2 (W Q - sum W Q0)
-            T G5[5];
+            // d/dq of 1/2 q^T K q + b^T q = K q + b, K from its upper triangle
+            const double* d = L.anch_data + ANCH_STRIDE * (int64_t)at;
+            T Kq[5];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) G5[c] = T(2) * (W * q0[c] - qw[c]);
-            T G[3][3], ga[5];
-            full_of(G5, G);
-            pT(G, ga);
+            for (int a = 0; a < 5; ++a) Kq[a] = T(d[15 + a]);
+            int t = 0;
 #pragma unroll
-            for (int c = 0; c < 5; ++c) g[c] += ga[c];
+            for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int b = a; b < 5; ++b, ++t) {
+                    const T k = T(d[t]);
+                    Kq[a] = fma_t(k, q0[b], Kq[a]);
+                    if (b != a) Kq[b] = fma_t(k, q0[a], Kq[b]);
+                }
+#pragma unroll
+            for (int c = 0; c < 5; ++c) g[c] += Kq[c];
         }
     }
 #pragma unroll
@@ -586,43 +590,55 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
     };
     auto slot_of = [](int i) { return (i + NS) & (NS - 1); };
 
-    // One loop body issues every global access, so the hardware wait counts
-    // are exact on all paths: iteration k drifts plane k (loaded by
-    // iteration k-1), loads plane k+1, and evaluates the force of plane k-1.
-    // Planes outside 0 .. zc+1 are loaded with out-of-range offsets and the
-    // force outside 1 .. zc is stored nowhere.
+    // Loads run one plane ahead: iteration j drifts plane j (loaded during
+    // iteration j-1), issues the loads of plane j+1, and evaluates and stores
+    // the force of plane j-1 from the LDS planes j-2 .. j.  Every path into
+    // the drift has the same stores queued behind the loads it waits for
+    // (the prologue stores to an offset past the end of the buffers, which
+    // the hardware drops), so the wait lets those stores drain.  Planes
+    // outside 0 .. zc+1 load from out-of-range offsets; forces outside
+    // 1 .. zc are stored nowhere.
+    // v1 and mask of the own site: `older` is the plane whose force is
+    // evaluated in this iteration, `newer` the plane just drifted.
+    T v1_older[5], v1_newer[5], q_unused[5];
+    uint32_t m_older = 0, m_newer = 0;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) { rq[c] = T(0); rv[c] = T(0); rf[c] = T(0); }
+    for (int c = 0; c < 5; ++c) { v1_older[c] = T(0); v1_newer[c] = T(0); }
+    load(0);
+    __builtin_amdgcn_sched_barrier(0);  // keep the dropped stores behind the loads
 #pragma unroll
-    for (int j = 0; j < ITEMS_PER_THREAD; ++j) { iq[j] = T(0); iv[j] = T(0); iF[j] = T(0); im[j] = 0; }
-    T v1_prev[5], v1_cur[5], q_unused[5];
-    uint32_t m_prev = 0, m_cur = 0;
+    for (int c = 0; c < 5; ++c) {
+        bst<T>(rF_out, NONE, c * cs, T(0));
+        if (STEP) { bst<T>(rq_out, NONE, c * cs, T(0)); bst<T>(rv_out, NONE, c * cs, T(0)); }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma clang loop unroll(disable)
+    for (int j = 0; j <= zc + 1; ++j) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) { v1_prev[c] = T(0); v1_cur[c] = T(0); }
-    for (int k = -1; k <= zc + 1; ++k) {
-#pragma unroll
-        for (int c = 0; c < 5; ++c) v1_prev[c] = v1_cur[c];
-        m_prev = m_cur;
-        drift(slot_of(k), q_unused, v1_cur, m_cur);
-        load(k + 1);
+        for (int c = 0; c < 5; ++c) v1_older[c] = v1_newer[c];
+        m_older = m_newer;
+        drift(slot_of(j), q_unused, v1_newer, m_newer);
+        __builtin_amdgcn_sched_barrier(0);
+        load(j + 1);
+        __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of this plane's stores
         lds_barrier();
         {
-            const int f = k - 1;  // plane whose force is evaluated
+            const int f = j - 1;  // plane whose force is evaluated
             const bool in_chunk = f >= 1;
             const int s = gx + L.nx * gy + nxy * (z0 + f - 1);
             const uint32_t off = (own_xy && in_chunk) ? (uint32_t)s * (uint32_t)sizeof(T) : NONE;
-            const bool live = own_xy && in_chunk && (m_prev & M_SIM);
+            const bool live = own_xy && in_chunk && (m_older & M_SIM);
             Stencil<T, L23, BULK> P;
             P.q = sq; P.m = sm;
             P.s[0] = slot_of(f - 1); P.s[1] = slot_of(f); P.s[2] = slot_of(f + 1);
             P.cx = tx + 1; P.cy = ty + 1;
             T F[5];
-            site_force<T, L23, BULK>(P, m_prev, L, s, F);
+            site_force<T, L23, BULK>(P, m_older, L, s, F);
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 const T Fc = live ? F[c] : T(0);
                 if (STEP) {
-                    const T v2 = live ? fma_t(hdt, F[c], v1_prev[c]) : T(0);
+                    const T v2 = live ? fma_t(hdt, F[c], v1_older[c]) : T(0);
                     const T qc = live ? P.at(0, 0, 0, c) : T(0);
                     bst<T>(rq_out, off, c * cs, qc);
                     bst<T>(rv_out, off, c * cs, v2);
@@ -861,7 +877,7 @@ __global__ __launch_bounds__(256) void k_energy(LatDev L, const T* __restrict__ 
     __shared__ double scratch[4][4];
     __shared__ int last_flag;
     const int64_t N = L.N;
-    double e_b = 0.0, e_d = 0.0, e_a = 0.0;
+    double e_b = 0.0, e_d = 0.0, e_a = 0.0, e_x = 0.0;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N;
          s += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t m = L.mask[s];
@@ -926,30 +942,30 @@ __global__ __launch_bounds__(256) void k_energy(LatDev L, const T* __restrict__ 
                         ed += L.L2 * Cf[j][i][j] * Cf[k][i][k] + L.L3 * Cf[j][i][k] * Cf[k][i][j];
         }
         e_d += ed;
+        double qe = 0.0;
+        for (int c = 0; c < 5; ++c) qe += L.ext[c] * q0[c];
+        e_x -= qe;
         if (m & M_ANCH) {
-            int lo = 0, hi = L.n_anch - 1, at = -1;
-            while (lo <= hi) {
-                int mid = (lo + hi) >> 1;
-                int64_t sv = L.anch_site[mid];
-                if (sv == s) { at = mid; break; }
-                if (sv < s) lo = mid + 1; else hi = mid - 1;
-            }
+            const int at = L.anch_index[s] - 1;
             if (at >= 0) {
-                const double* d = L.anch_data + 7 * (int64_t)at;
-                double Qw[3][3];
-                full_of(d + 1, Qw);
-                double cross = 0.0;
-                for (int i = 0; i < 3; ++i)
-                    for (int j = 0; j < 3; ++j) cross += Q[i][j] * Qw[i][j];
-                e_a += d[0] * t2 - 2.0 * cross + d[6];
+                // 1/2 q^T K q + b^T q + c
+                const double* d = L.anch_data + ANCH_STRIDE * (int64_t)at;
+                double quad = 0.0, lin = 0.0;
+                int t = 0;
+                for (int a = 0; a < 5; ++a) {
+                    lin += d[15 + a] * q0[a];
+                    for (int b = a; b < 5; ++b, ++t)
+                        quad += (b == a ? 0.5 : 1.0) * d[t] * q0[a] * q0[b];
+                }
+                e_a += quad + lin + d[20];
             }
         }
     }
-    double r[4] = {e_b, e_d, e_a, 0.0};
+    double r[4] = {e_b, e_d, e_a, e_x};
     block_reduce4(r, scratch);
     if (threadIdx.x == 0) {
         double* p = partials + 4 * (int64_t)blockIdx.x;
-        p[0] = r[0]; p[1] = r[1]; p[2] = r[2]; p[3] = 0.0;
+        p[0] = r[0]; p[1] = r[1]; p[2] = r[2]; p[3] = r[3];
         __threadfence();
         unsigned t = atomicAdd(ticket, 1u);
         last_flag = (t == gridDim.x - 1);
@@ -960,12 +976,12 @@ __global__ __launch_bounds__(256) void k_energy(LatDev L, const T* __restrict__ 
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
         const volatile double* p = partials + 4 * (int64_t)b;
-        s4[0] += p[0]; s4[1] += p[1]; s4[2] += p[2];
+        s4[0] += p[0]; s4[1] += p[1]; s4[2] += p[2]; s4[3] += p[3];
     }
     __syncthreads();
     block_reduce4(s4, scratch);
     if (threadIdx.x == 0) {
-        out->bulk = s4[0]; out->elastic = s4[1]; out->anch = s4[2];
+        out->bulk = s4[0]; out->elastic = s4[1]; out->anch = s4[2]; out->ext = s4[3];
         *ticket = 0;
         __threadfence();
     }

@@ -18,12 +18,16 @@ constexpr uint8_t M_SIM = 0x40;
 constexpr uint8_t M_ANCH = 0x80;
 constexpr uint8_t M_FULL = 0x7F;  // simulated bulk site with all six neighbours
 
+// Anchoring form of one site: upper triangle of K (15), b (5), c (1) with
+// f = 1/2 q^T K q + b^T q + c.
+constexpr int ANCH_STRIDE = 21;
+
 // Host-side rasterization result.
 struct Geometry {
     std::vector<uint8_t> type;       // 0 bulk, 1 boundary, 2 object
     std::vector<uint8_t> mask;       // neighbour mask (above)
     std::vector<int64_t> anch_site;  // sorted
-    std::vector<double> anch_data;   // 7 per anchored site
+    std::vector<double> anch_data;   // ANCH_STRIDE per anchored site
     int64_t n_sim = 0;
 };
 
@@ -34,8 +38,14 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
 
 // Tile geometry of the fused kernel: TX x TY columns, each block marches
 // zc planes.
-constexpr int TX = 32;
-constexpr int TY = 8;
+#ifndef LQ_TILE_X
+#define LQ_TILE_X 32
+#endif
+#ifndef LQ_TILE_Y
+#define LQ_TILE_Y 8
+#endif
+constexpr int TX = LQ_TILE_X;
+constexpr int TY = LQ_TILE_Y;
 constexpr int NTHREADS = TX * TY;
 
 // Device view of a lattice.
@@ -46,8 +56,9 @@ struct LatDev {
     const uint8_t* mask;
     const uint8_t* tile_bulk;  // 1: every site of the padded tile has mask M_FULL
     int n_anch;
-    const int32_t* anch_site;  // sorted
-    const double* anch_data;   // 7 per anchored site
+    const int32_t* anch_index;  // per site: 1 + row of anch_data, 0 when not anchored
+    const double* anch_data;    // ANCH_STRIDE per anchored site
+    double ext[5];              // constant external-field force per simulated site
     double A, B, C, L1, L2, L3;
     int zc, ntx, nty, ntz;
 };
@@ -88,7 +99,7 @@ struct MemberDev {
 };
 
 struct EnergyOut {
-    double bulk, elastic, anch;
+    double bulk, elastic, anch, ext;
 };
 
 // Kernel launchers (kernels.hip).  All enqueue on stream.

@@ -16,7 +16,9 @@ LIB_PATH = os.path.join(HERE, "liblqfire.so")
 LQ_OK, LQ_EINVAL, LQ_EUNSUPPORTED, LQ_ENOMEM, LQ_EHIP, LQ_ENONFINITE, LQ_ESTATE = 0, -1, -2, -3, -4, -5, -6
 LQ_F64, LQ_F32 = 0, 1
 LQ_OBJ_WALL, LQ_OBJ_SPHERE, LQ_OBJ_PATTERNED_WALL = 1, 2, 3
-LQ_LAW_ND, LQ_LAW_RP = 0, 1
+LQ_LAW_ND, LQ_LAW_RP, LQ_LAW_FG = 0, 1, 2
+LAWS = {"nd": LQ_LAW_ND, "rp": LQ_LAW_RP, "fg": LQ_LAW_FG}
+ANCH_STRIDE = 21
 LQ_DIR_NORMAL, LQ_DIR_FIXED = 0, 1
 RUNNING, CONVERGED, MAX_STEPS, NONFINITE = 0, 1, 2, 3
 
@@ -51,7 +53,7 @@ class SiteAnchor(C.Structure):
 
 class EnergyTerms(C.Structure):
     _fields_ = [("bulk", C.c_double), ("elastic", C.c_double), ("anchoring", C.c_double),
-                ("total", C.c_double), ("n_sim", C.c_int64)]
+                ("external", C.c_double), ("total", C.c_double), ("n_sim", C.c_int64)]
 
 
 class FireParams(C.Structure):
@@ -86,6 +88,7 @@ def lib():
             "lq_lattice_create": (C.c_int, [C.POINTER(Params), vp, C.POINTER(vp)]),
             "lq_lattice_destroy": (C.c_int, [vp]),
             "lq_bulk_S0": (C.c_double, [vp]),
+            "lq_set_field": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), i32]),
             "lq_set_boundaries": (C.c_int, [vp, C.POINTER(Object), i32, C.POINTER(SiteAnchor), i64,
                                             C.POINTER(C.c_int64), i64]),
             "lq_rasterize": (C.c_int, [C.POINTER(Params), C.POINTER(Object), i32, C.POINTER(SiteAnchor),
@@ -138,7 +141,7 @@ def make_objects(objects):
         t = arr[i]
         t.kind = {"wall": LQ_OBJ_WALL, "sphere": LQ_OBJ_SPHERE,
                   "patterned_wall": LQ_OBJ_PATTERNED_WALL}[o["kind"]]
-        t.law = {"nd": LQ_LAW_ND, "rp": LQ_LAW_RP}[o.get("law", "nd")]
+        t.law = LAWS[o.get("law", "nd")]
         d = o.get("dir", "normal")
         if isinstance(d, str):
             if d != "normal":
@@ -158,13 +161,21 @@ def make_objects(objects):
     return arr, len(objects)
 
 
+def _is_fg(law, W):
+    return law == "fg" or (law == "rp" and float(W) < 0)
+
+
 def make_records(records):
+    """Per-site records {site, law, W, n0} (Nobili-Durand) or {site, law, W, nu}
+    (Fournier-Galatola: law "fg", or "rp" with W < 0)."""
     arr = (SiteAnchor * max(len(records), 1))()
     for i, r in enumerate(records):
+        law = r.get("law", "nd")
         arr[i].site = int(r["site"])
-        arr[i].law = {"nd": LQ_LAW_ND, "rp": LQ_LAW_RP}[r.get("law", "nd")]
+        arr[i].law = LAWS[law]
         arr[i].W = float(r["W"])
-        arr[i].n0 = (C.c_double * 3)(*[float(x) for x in r["n0"]])
+        v = r["nu"] if _is_fg(law, r["W"]) else r["n0"]
+        arr[i].n0 = (C.c_double * 3)(*[float(x) for x in v])
     return arr, len(records)
 
 
@@ -174,7 +185,9 @@ def make_fire_params(dt0=1e-3, dt_max=1e-2, alpha0=0.99, f_inc=1.1, f_dec=0.5, f
 
 
 def rasterize(shape, periodic, objects=(), site_records=(), object_sites=(), A=-0.172, B=-2.12, C_=1.73):
-    """Host-only rasterization (lq_rasterize): (types, anch_site, anch_data[n, 7]) as numpy."""
+    """Host-only rasterization (lq_rasterize): (types, anch_site, anch_data[n, ANCH_STRIDE]) as
+    numpy; row i holds the upper triangle of K (15), b (5) and c of the site's anchoring energy
+    1/2 q^T K q + b^T q + c."""
     import numpy as np
     p = make_params(shape, periodic, A=A, B=B, C_=C_)
     objs, no = make_objects(list(objects))
@@ -188,7 +201,7 @@ def rasterize(shape, periodic, objects=(), site_records=(), object_sites=(), A=-
     _check(lib().lq_rasterize(*args, None, None, 0))
     n = n_anch.value
     sites = np.zeros(max(n, 1), dtype=np.int64)
-    data = np.zeros((max(n, 1), 7))
+    data = np.zeros((max(n, 1), ANCH_STRIDE))
     _check(lib().lq_rasterize(*args, sites.ctypes.data_as(C.POINTER(C.c_int64)),
                               data.ctypes.data_as(C.POINTER(C.c_double)), n))
     return types, sites[:n], data[:n]
@@ -257,6 +270,17 @@ class Lattice:
                                        osites.ctypes.data_as(C.POINTER(C.c_int64)), len(osites)), self.h)
         self._bound = None
 
+    def set_field(self, fields=()):
+        """fields: (h, chi) pairs, each adding -(chi/3) h.Q.h per simulated site."""
+        import numpy as np
+        fields = list(fields)
+        h = np.ascontiguousarray(np.array([np.asarray(f[0], dtype=np.float64) for f in fields]
+                                          if fields else np.zeros((1, 3))).reshape(-1))
+        chi = np.ascontiguousarray(np.array([float(f[1]) for f in fields] if fields else [0.0]))
+        _check(lib().lq_set_field(self.h, h.ctypes.data_as(C.POINTER(C.c_double)),
+                                  chi.ctypes.data_as(C.POINTER(C.c_double)), len(fields)), self.h)
+        self._bound = None
+
     def set_uniaxial(self, directors, q, S=None):
         """directors: float64 CUDA tensor (3, N) of unit vectors."""
         S = self.S0 if S is None else float(S)
@@ -275,7 +299,7 @@ class Lattice:
         out = EnergyTerms()
         _check(lib().lq_energy(self.h, self._field(q, "q"), C.byref(out)), self.h)
         return {"bulk": out.bulk, "elastic": out.elastic, "anchoring": out.anchoring,
-                "total": out.total, "n_sim": out.n_sim}
+                "external": out.external, "total": out.total, "n_sim": out.n_sim}
 
     def workspace_bytes(self):
         return int(lib().lq_workspace_bytes(self.h))
@@ -366,6 +390,10 @@ def set_boundaries(lat: Lattice, objects=(), site_records=(), object_sites=()):
     lat.set_boundaries(objects, site_records, object_sites)
 
 
+def set_field(lat: Lattice, fields=()):
+    lat.set_field(fields)
+
+
 def compute_forces(lat: Lattice, q, F=None):
     return lat.compute_forces(q, F)
 
@@ -388,6 +416,8 @@ def lattice_from_config(cfg, prec=None, **kw) -> Lattice:
                   L1=cfg["L1"], L2=cfg.get("L2", 0.0), L3=cfg.get("L3", 0.0), **kw)
     if cfg.get("objects"):
         lat.set_boundaries(cfg["objects"])
+    if cfg.get("fields"):
+        lat.set_field(cfg["fields"])
     return lat
 
 

@@ -31,22 +31,29 @@ def test_library_exports_every_declared_function():
     assert not missing, missing
 
 
-def _oracle_site_sums(ora, shape, periodic, objects, records=(), object_sites=()):
-    s0 = ora.S0(A, B, C)
-    types, ps, pw, pq = ora.rasterize(shape, periodic, list(objects), s0, records, object_sites)
-    order = np.argsort(ps, kind="stable")
-    sites = np.unique(ps)
-    sums = np.zeros((len(sites), 7))
-    idx = np.searchsorted(sites, ps)
-    tr2 = (pq[:, 0] ** 2 + pq[:, 3] ** 2 + (pq[:, 0] + pq[:, 3]) ** 2
-           + 2 * (pq[:, 1] ** 2 + pq[:, 2] ** 2 + pq[:, 4] ** 2))
-    for i in order:
-        sums[idx[i], 0] += pw[i]
-        sums[idx[i], 1:6] += pw[i] * pq[i]
-        sums[idx[i], 6] += pw[i] * tr2[i]
-    return types, sites, sums
+def _zero_strength(objs, recs):
+    """The same geometry with every anchoring term at zero strength (a
+    degenerate-planar Rapini-Papoular term keeps its Fournier-Galatola form)."""
+    def z(d):
+        if d.get("law") == "rp" and d["W"] < 0:
+            return dict(d, law="fg", W=0.0)
+        return dict(d, W=0.0)
+    return [z(o) for o in objs], [z(r) for r in recs]
 
 
+def _form_terms(sites, data, q):
+    """Energy and force of the library's per-site forms 1/2 q^T K q + b^T q + c."""
+    iu = np.triu_indices(5)
+    e = 0.0
+    F = np.zeros((5, q.shape[1]))
+    for s, d in zip(sites, data):
+        K = np.zeros((5, 5))
+        K[iu] = d[:15]
+        K = K + np.triu(K, 1).T
+        x = q[:, s]
+        e += 0.5 * x @ K @ x + d[15:20] @ x + d[20]
+        F[:, s] = -(K @ x + d[15:20])
+    return e, F
 GEOMS = {
     "colloid_slab32": lambda: (synth.colloid_slab(32)["shape"], (True,) * 3, synth.colloid_slab(32)["objects"], (), ()),
     "multi_colloid64": lambda: ((64, 64, 64), (True,) * 3,
@@ -61,6 +68,17 @@ GEOMS = {
         dict(kind="wall", axis=1, plane=0, law="nd", W=0.3, dir=(0.0, 0.0, 1.0))],
         [dict(site=100, law="rp", W=2.0, n0=(1.0, 0.0, 1.0)), dict(site=100, law="nd", W=0.5, n0=(0, 1, 0)),
          dict(site=200, law="nd", W=1.0, n0=(0.2, 0.3, 0.9))], [300, 301, 302]),
+    "fg_walls_and_sphere": lambda: ((18, 16, 14), (True, True, False), [
+        dict(kind="wall", axis=2, plane=0, law="fg", W=0.8),
+        dict(kind="wall", axis=2, plane=13, law="rp", W=-2.5),
+        dict(kind="sphere", center=(8.2, 7.7, 6.9), radius=3.6, law="fg", W=1.3)], (), ()),
+    "fg_mixed_records_patterned": lambda: ((20, 12, 9), (True, True, True), [
+        dict(kind="patterned_wall", axis=2, plane=0, law="fg", W=0.6, pitch=(10, 6), offset=(4.5, 2.5),
+             count=(2, 2)),
+        dict(kind="sphere", center=(3.0, 5.0, 4.5), radius=2.5, law="nd", W=0.9, dir="normal"),
+        dict(kind="wall", axis=0, plane=15, law="rp", W=-1.0, dir=(0.0, 1.0, 0.0))],
+        [dict(site=1000, law="fg", W=0.4, nu=(1.0, 2.0, 2.0)), dict(site=1000, law="rp", W=1.0, n0=(0, 0, 1)),
+         dict(site=1500, law="rp", W=-3.0, nu=(0.0, 0.6, 0.8))], [1700]),
     "overlapping_objects": lambda: ((24, 24, 24), (True,) * 3, [
         dict(kind="sphere", center=(10.0, 10.0, 10.0), radius=5.0, law="rp", W=3.0, dir="normal"),
         dict(kind="sphere", center=(15.5, 10.0, 10.0), radius=4.0, law="rp", W=6.0, dir="normal"),
@@ -70,12 +88,26 @@ GEOMS = {
 
 @pytest.mark.parametrize("name", sorted(GEOMS))
 def test_rasterizer_matches_oracle(ora, name):
+    """Site types and anchored sites equal the oracle's; each site's stored
+    quadratic form reproduces the oracle's anchoring energy and the oracle's
+    anchoring force (its force minus that of the same geometry at zero
+    strength) for random fields and at q = 0."""
     shape, periodic, objs, recs, osites = GEOMS[name]()
-    t_o, s_o, d_o = _oracle_site_sums(ora, shape, periodic, objs, recs, osites)
+    p = ora.Problem(shape, periodic, A, B, C, objects=objs, site_records=recs, object_sites=osites)
+    o0, r0 = _zero_strength(objs, recs)
+    p0 = ora.Problem(shape, periodic, A, B, C, objects=o0, site_records=r0, object_sites=osites)
     t_l, s_l, d_l = lqfire.rasterize(shape, periodic, objs, recs, osites)
-    assert np.array_equal(t_o, t_l)
-    assert np.array_equal(s_o, s_l)
-    assert np.abs(d_o - d_l).max() <= 1e-14 * max(1.0, np.abs(d_o).max())
+    assert np.array_equal(p.types, t_l)
+    assert np.array_equal(np.unique(p.pair_site), s_l)
+    for seed in (0, 31, 32):
+        q = synth.random_field(seed, p.N).reshape(5, -1) if seed else np.zeros((5, p.N))
+        q[:, p.types == 2] = 0.0
+        e_form, F_form = _form_terms(s_l, d_l, q)
+        _, terms = p.energy(q, terms=True)
+        assert abs(e_form - terms[2]) <= 1e-13 * max(1.0, abs(terms[2]))
+        F_anch = (p.forces(q) - p0.forces(q)).reshape(5, -1)
+        scale = max(1.0, np.abs(F_anch).max())
+        assert np.abs(F_form - F_anch).max() <= 1e-12 * scale
 
 
 def test_rasterizer_counts_for_the_colloid_slab():
@@ -101,9 +133,12 @@ def test_error_codes_on_the_host():
                                         [dict(kind="wall", axis=2, plane=8, W=1.0)])) == lqfire.LQ_EINVAL
     assert _rc(lambda: lqfire.rasterize(box, (True, True, True),
                                         [dict(kind="sphere", center=(1, 1, 1), radius=-1.0, W=1.0)])) == lqfire.LQ_EINVAL
-    assert _rc(lambda: lqfire.rasterize(box, (True, True, True),
-                                        [dict(kind="sphere", center=(4, 4, 4), radius=2.0, law="rp",
-                                              W=-1.0)])) == lqfire.LQ_EUNSUPPORTED
+    for law in ("nd", "fg"):
+        assert _rc(lambda: lqfire.rasterize(box, (True, True, True),
+                                            [dict(kind="sphere", center=(4, 4, 4), radius=2.0, law=law,
+                                                  W=-1.0)])) == lqfire.LQ_EINVAL
+    assert _rc(lambda: lqfire.rasterize(box, (True, True, True), [],
+                                        [dict(site=5, law="fg", W=1.0, nu=(0, 0, 0))])) == lqfire.LQ_EINVAL
     assert _rc(lambda: lqfire.rasterize((2, 8, 8), (True, True, True))) == lqfire.LQ_EINVAL
     assert _rc(lambda: lqfire.rasterize(box, (True, True, True), [dict(kind="wall", axis=2, plane=0, W=1.0)],
                                         [dict(site=8 * 8 * 0 + 3, W=1.0, n0=(1, 0, 0))])) == lqfire.LQ_EINVAL

@@ -29,12 +29,14 @@ def _gpu():
 
 
 def pair(ora, shape, periodic=(True, True, True), L2=0.0, L3=0.0, objects=(), records=(), osites=(),
-         prec="f64", L1=2.32):
+         prec="f64", L1=2.32, fields=()):
     p = ora.Problem(shape, periodic, L1=L1, L2=L2, L3=L3, objects=objects, site_records=records,
-                    object_sites=osites)
+                    object_sites=osites, fields=fields)
     lat = lqfire.Lattice(shape, periodic, prec, L1=L1, L2=L2, L3=L3)
     if objects or records or len(osites):
         lat.set_boundaries(objects, records, osites)
+    if fields:
+        lat.set_field(fields)
     return p, lat
 
 
@@ -62,6 +64,21 @@ CASES = {
         dict(kind="wall", axis=2, plane=8, law="rp", W=2.0, dir="normal")],
         records=[dict(site=1000, law="nd", W=0.4, n0=(1, 2, 2)), dict(site=1000, law="rp", W=1.0, n0=(0, 0, 1))],
         osites=[2000, 2001, 2040]),
+    "fg_walls_sphere_field_L23": dict(shape=(26, 22, 20), periodic=(True, True, False), L2=1.16, L3=0.7,
+                                      objects=[
+        dict(kind="wall", axis=2, plane=0, law="fg", W=0.8),
+        dict(kind="wall", axis=2, plane=19, law="rp", W=-2.5),
+        dict(kind="sphere", center=(12.2, 10.7, 9.4), radius=4.6, law="fg", W=1.3)],
+        fields=[((0.3, 0.1, 0.5), 2.0), ((1.0, 0.0, 0.0), -0.7)]),
+    "fg_records_patterned_L1": dict(shape=(20, 12, 9), objects=[
+        dict(kind="patterned_wall", axis=2, plane=0, law="fg", W=0.6, pitch=(10, 6), offset=(4.5, 2.5),
+             count=(2, 2)),
+        dict(kind="sphere", center=(3.0, 5.0, 4.5), radius=2.5, law="nd", W=0.9, dir="normal"),
+        dict(kind="wall", axis=0, plane=15, law="rp", W=-1.0)],
+        records=[dict(site=1000, law="fg", W=0.4, nu=(1.0, 2.0, 2.0)), dict(site=1000, law="rp", W=1.0, n0=(0, 0, 1)),
+                 dict(site=1500, law="rp", W=-3.0, nu=(0.0, 0.6, 0.8))], osites=[1700]),
+    "field_only_open_L23": dict(shape=(37, 6, 5), periodic=(False, True, False), L2=0.9, L3=1.3,
+                                fields=[((0.0, 0.8, 0.6), 1.5)]),
     "sandwiched_plane_L23": dict(shape=(66, 5, 3), L2=1.16, L3=0.3, objects=[
         dict(kind="wall", axis=2, plane=0, law="nd", W=0.7, dir=(0.0, 1.0, 0.0)),
         dict(kind="wall", axis=2, plane=2, law="nd", W=0.2, dir="normal")]),
@@ -84,13 +101,13 @@ def test_forces_and_energy_fp64(ora, name):
     scale = np.abs(F_ora).max()
     assert np.abs(F - F_ora).max() <= 1e-12 * scale
     assert abs(e["total"] - E_ora) <= 1e-12 * max(1.0, abs(E_ora))
-    for k, key in enumerate(("bulk", "elastic", "anchoring")):
+    for k, key in enumerate(("bulk", "elastic", "anchoring", "external")):
         assert abs(e[key] - t_ora[k]) <= 1e-12 * max(1.0, abs(t_ora[k]))
     assert e["n_sim"] == p.n_sim
 
 
 @pytest.mark.parametrize("name", ["bulk32_L1", "ragged_periodic_L23", "colloid_slab24_L23",
-                                  "patterned_records_L23"])
+                                  "patterned_records_L23", "fg_walls_sphere_field_L23"])
 def test_forces_and_energy_fp32(ora, name):
     c = dict(CASES[name])
     say(f"[forces f32] {name} {c['shape']}")
@@ -162,6 +179,72 @@ def test_fire_trajectory_walls_colloid_L23(ora):
     p, lat = pair(ora, cfg["shape"], L2=1.16, L3=1.16, objects=cfg["objects"])
     q0 = p.uniaxial(synth.random_directors(5, p.N))
     _fire_trajectory(ora, p, lat, q0, 150, 10, 1e-10)
+
+
+def test_fire_trajectory_fg_sphere_field_L23(ora):
+    """Degenerate planar (Fournier-Galatola) walls and colloid in two
+    external fields: the force field agrees to 1e-10 over 150 steps."""
+    c = CASES["fg_walls_sphere_field_L23"]
+    say("[fire] fg walls + sphere + fields L23 150 steps")
+    p, lat = pair(ora, c["shape"], c["periodic"], L2=c["L2"], L3=c["L3"], objects=c["objects"],
+                  fields=c["fields"])
+    q0 = p.uniaxial(synth.random_directors(9, p.N))
+    _fire_trajectory(ora, p, lat, q0, 150, 10, 1e-10)
+
+
+def test_minimize_fg_slab_reaches_exact_planar_minimum():
+    """Between two degenerate planar walls every uniform in-plane uniaxial
+    state at S0 has zero anchoring energy, so it is an exact minimum with
+    E = N_sim f0 (Eq. f0).  From a perturbed in-plane start FIRE reaches it:
+    Qzz = -S0/2 and Qxz = Qyz = 0 at every simulated site."""
+    say("[minimize] fg slab")
+    objs = [dict(kind="wall", axis=2, plane=0, law="fg", W=0.8),
+            dict(kind="wall", axis=2, plane=13, law="rp", W=-3.0)]
+    lat = lqfire.Lattice((24, 20, 14), L2=1.16, L3=0.7)
+    lat.set_boundaries(objs)
+    d = synth.random_directors(13, lat.N).reshape(3, -1)
+    n = np.array([0.8, 0.6, 0.0])[:, None] + 0.3 * d
+    n /= np.sqrt((n * n).sum(axis=0))
+    q = lat.set_uniaxial(to_dev(n, torch.float64), lat.empty())
+    rep, q, v, F = lat.minimize(lqfire.make_fire_params(force_tol=1e-10, max_steps=80000), q)
+    assert rep.status == lqfire.CONVERGED, rep.as_dict()
+    s0 = lat.S0
+    f0 = 0.75 * A * s0 ** 2 + 0.25 * B * s0 ** 3 + 9.0 / 16.0 * C * s0 ** 4
+    e = lat.energy(q)
+    assert abs(e["anchoring"]) <= 1e-12 * abs(e["total"])
+    assert abs(e["total"] - e["n_sim"] * f0) <= 1e-9 * abs(e["n_sim"] * f0)
+    qa = q.cpu().numpy().reshape(5, 14, -1)[:, 1:13]
+    assert np.abs(-(qa[0] + qa[3]) + 0.5 * s0).max() < 1e-6
+    assert np.abs(qa[2]).max() < 1e-6 and np.abs(qa[4]).max() < 1e-6
+    say(f"  steps {rep.step}")
+
+
+def test_minimize_bulk_in_field_reaches_field_aligned_state():
+    """Periodic bulk in a field h with chi > 0 (sec. II.C): the minimum is
+    uniaxial along h with S solving d/dS [3/4 A S^2 + 1/4 B S^3 + 9/16 C S^4
+    - chi |h|^2 S / 3] = 0 near S0 (h.Q.h = S |h|^2 for n along h)."""
+    say("[minimize] bulk in field")
+    h = np.array([0.0, 0.6, 0.8])
+    chi = 0.9
+    lat = lqfire.Lattice((16, 12, 10))
+    lat.set_field([(h, chi)])
+    d = synth.random_directors(14, lat.N).reshape(3, -1)
+    n = np.array([1.0, 1.0, 0.0])[:, None] / np.sqrt(2.0) + 0.2 * d
+    n /= np.sqrt((n * n).sum(axis=0))
+    q = lat.set_uniaxial(to_dev(n, torch.float64), lat.empty())
+    rep, q, v, F = lat.minimize(lqfire.make_fire_params(force_tol=1e-10, max_steps=80000), q)
+    assert rep.status == lqfire.CONVERGED, rep.as_dict()
+    roots = np.roots([9.0 / 4.0 * C, 3.0 / 4.0 * B, 1.5 * A, -chi / 3.0])
+    roots = roots[np.abs(roots.imag) < 1e-12].real
+    S = roots[np.argmin(np.abs(roots - lat.S0))]
+    f = 0.75 * A * S ** 2 + 0.25 * B * S ** 3 + 9.0 / 16.0 * C * S ** 4 - chi / 3.0 * S
+    e = lat.energy(q)
+    assert abs(e["total"] - lat.N * f) <= 1e-9 * abs(lat.N * f)
+    assert abs(e["external"] + lat.N * chi / 3.0 * S) <= 1e-9 * abs(lat.N * chi * S)
+    Q = 1.5 * S * (np.outer(h, h) - np.eye(3) / 3)
+    qx = np.array([Q[0, 0], Q[0, 1], Q[0, 2], Q[1, 1], Q[1, 2]])
+    assert np.abs(q.cpu().numpy().reshape(5, -1) - qx[:, None]).max() < 1e-6
+    say(f"  steps {rep.step}, S {S:.6f} (S0 {lat.S0:.6f})")
 
 
 def test_fire_steps_resume_bitwise():
@@ -291,6 +374,16 @@ def test_error_paths():
     assert rep.status == lqfire.MAX_STEPS and rep.step == 0
     with pytest.raises(ValueError):
         lat.compute_forces(q.cpu())
+    # fields: non-finite values are refused; a new field unbinds FIRE
+    with pytest.raises(lqfire.LQError) as e:
+        lat.set_field([((1.0, float("inf"), 0.0), 1.0)])
+    assert e.value.code == lqfire.LQ_EINVAL
+    lat.fire_init(prm, q, v, F)
+    lat.fire_step(1)
+    lat.set_field([((1.0, 0.0, 0.0), 0.5)])
+    with pytest.raises(lqfire.LQError) as e:
+        lat.fire_step(1)
+    assert e.value.code == lqfire.LQ_ESTATE
 
 
 def _sampled_sites(p, rng, n):

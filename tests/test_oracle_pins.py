@@ -550,3 +550,71 @@ def test_fire_at_a_stationary_point_restarts(ora):
     assert taken == 4 and st.restarts == 4
     assert np.all(v == 0.0) and np.array_equal(q, q0)
     assert np.array_equal(tr[:, 4], 0.01 * 0.5 ** np.arange(1, 5))
+
+
+# ---------------------------------------------------------------- degenerate planar + fields
+def test_fournier_galatola_uniaxial_closed_form(ora):
+    """Sec. II.D, Eq. (planarDegenerate) with the projector P Qt P: for a
+    uniaxial Q at S0 with director n and a surface normal nu (c = n.nu),
+    Qt - P Qt P = 3/2 S0 [c (n nu + nu n) - c^2 nu nu], so the density is
+    W (9/4) S0^2 (2 c^2 - c^4): zero for every n in the surface plane, and
+    (9/2) S0^2 W c^2 for small c, i.e. W_RP = 9 S0^2 W_FG (a negative
+    Rapini-Papoular strength enters as |W_RP| / (9 S0^2))."""
+    rng = np.random.default_rng(31)
+    for law, W in (("fg", 0.7), ("rp", -4.0)):
+        objs = [dict(kind="wall", axis=2, plane=0, law=law, W=W)]
+        p = ora.Problem((3, 3, 3), L1=2.32, objects=objs)
+        Wfg = W if law == "fg" else -W / (9 * p.S0 ** 2)
+        for _ in range(4):
+            n = rng.standard_normal(3)
+            n /= np.linalg.norm(n)
+            q = p.uniaxial(np.repeat(n[:, None], p.N, axis=1))
+            _, t = p.energy(q, terms=True)
+            c = n[2]
+            ref = 18 * Wfg * 2.25 * p.S0 ** 2 * (2 * c * c - c ** 4)
+            assert abs(t[2] - ref) <= 1e-13 * max(1.0, abs(ref))
+        # degenerate: any in-plane director costs nothing
+        a = rng.uniform(0, 2 * np.pi)
+        q = p.uniaxial(np.repeat(np.array([[np.cos(a)], [np.sin(a)], [0.0]]), p.N, axis=1))
+        assert abs(p.energy(q, terms=True)[1][2]) < 1e-15
+
+
+def test_external_field_uniaxial_reduction(ora):
+    """Sec. II.C: -(1/3) chi h.Q.h at a uniaxial Q equals
+    -(1/2) chi S (h.n)^2 up to the n-independent chi S |h|^2 / 6."""
+    rng = np.random.default_rng(32)
+    h = np.array([0.3, -1.2, 0.5])
+    E = np.array([1.0, 0.2, 0.0])
+    p = ora.Problem((3, 3, 3), L1=0.0, fields=[(h, 0.8), (E, -0.3)])
+    for _ in range(4):
+        n = rng.standard_normal(3)
+        n /= np.linalg.norm(n)
+        S = rng.uniform(0.1, 0.9)
+        q = p.uniaxial(np.repeat(n[:, None], p.N, axis=1), S)
+        _, t = p.energy(q, terms=True)
+        ref = 0.0
+        for v, chi in ((h, 0.8), (E, -0.3)):
+            ref += -0.5 * chi * S * (v @ n) ** 2 + chi * S * (v @ v) / 6.0
+        assert abs(t[3] / p.N - ref) <= 1e-14 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("name", ["fg_walls_sphere_fields", "fg_records"])
+def test_forces_exact_gradient_planar_and_fields(ora, name):
+    """Forces stay the exact gradient with degenerate planar anchoring and
+    external fields switched on."""
+    if name == "fg_walls_sphere_fields":
+        kw = dict(shape=(4, 3, 5), L2=0.9, L3=0.4, fields=[((0.2, 0.5, -1.0), 0.7)], objects=[
+            dict(kind="wall", axis=2, plane=0, law="fg", W=0.8),
+            dict(kind="wall", axis=2, plane=4, law="rp", W=-3.0),
+            dict(kind="sphere", center=(1.7, 1.2, 2.0), radius=1.1, law="rp", W=-2.0)])
+    else:
+        kw = dict(shape=(3, 4, 3), L2=0.0, L3=0.0, fields=[((1.0, 0.0, 0.0), -0.5)],
+                  site_records=[dict(site=7, law="fg", W=1.3, nu=(0.2, 0.9, 0.3)),
+                                dict(site=7, law="nd", W=0.4, n0=(1, 0, 0)),
+                                dict(site=20, law="rp", W=-5.0, nu=(0, 0, 1))])
+    shape = kw.pop("shape")
+    p = ora.Problem(shape, L1=2.32, **kw)
+    q = rand_q(p, seed=41)
+    F = p.forces(q)
+    Ffd = five_point_forces(p, q)
+    assert np.abs(F - Ffd).max() <= 1e-10 * np.abs(F).max()
