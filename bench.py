@@ -198,6 +198,24 @@ def serving_leg(n_requests=512, rate=20.0):
     return out
 
 
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration(reps=5):
+    """Plain device-to-device copies of COPY_BYTES each.  Under rocprofv3
+    --pmc FETCH_SIZE (or WRITE_SIZE) the per-dispatch counter of these copies,
+    against the known COPY_BYTES read and written, gives the factor that turns
+    the counter into HBM bytes."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "reps": reps}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,7 +226,12 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain device copies of a known size (HBM counter scale)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs one GPU only: the hot path here is a single-GPU lattice "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)

@@ -70,7 +70,7 @@ int lq_lattice_destroy(lq_lattice* lat);
 /* S0 of Eq. (S0def) for the lattice's A, B, C (NaN when it has no real value). */
 double lq_bulk_S0(const lq_lattice* lat);
 
-/* ---- geometry (sec. III.B site types; sec. II.D anchoring) ---- */
+/* ---- geometry (sec. III.B site types; sec. II.A.4 anchoring) ---- */
 #define LQ_OBJ_WALL 1           /* the lattice plane coordinate[axis] == plane */
 #define LQ_OBJ_SPHERE 2         /* sites with |x - center|^2 < radius^2, minimum image on periodic axes */
 #define LQ_OBJ_PATTERNED_WALL 3 /* a wall whose preferred director is the in-plane radial unit
@@ -118,7 +118,7 @@ typedef struct {
  * Nobili-Durand anchoring uses Q0 = 3/2 S0 (n0 n0 - I/3); Fournier-Galatola
  * anchoring uses the surface normal nu of the object (the wall axis, or the
  * unit vector from a sphere's centre) and ignores dir_mode and the patterned
- * wall's radial director (sec. II.D).  Host arrays; any may be NULL
+ * wall's radial director (sec. II.A.4).  Host arrays; any may be NULL
  * when its count is 0.  LQ_EINVAL on a bad object, a record at an object site
  * or out of range, or S0 not real while anchoring is requested. */
 int lq_set_boundaries(lq_lattice* lat, const lq_object* objs, int32_t n_objs,
@@ -153,7 +153,7 @@ int lq_set_uniaxial(lq_lattice* lat, const double* directors, double S, void* q)
  * objects.  q and F: device, 5*N elements. */
 int lq_compute_forces(lq_lattice* lat, const void* q, void* F);
 
-/* External fields (sec. II.C, external fields free energy): each field
+/* External fields (sec. II.A.3): each field
  * adds -(chi/3) h_i Q_ij h_j at every simulated site, where h is the field
  * vector and chi the product of the vacuum constant and the anisotropic
  * susceptibility (mu0 dchi for H, eps0 deps for E), in units of |A|.

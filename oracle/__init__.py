@@ -56,7 +56,13 @@ class FireState(C.Structure):
                 ("normv", C.c_double), ("maxF", C.c_double)]
 
 
+class DescentParams(C.Structure):
+    _fields_ = [("method", C.c_int32), ("pad", C.c_int32), ("dt", C.c_double),
+                ("momentum", C.c_double), ("force_tol", C.c_double), ("max_steps", C.c_int64)]
+
+
 RUNNING, CONVERGED, MAX_STEPS, NONFINITE = 0, 1, 2, 3
+GD, NESTEROV = 1, 2
 
 FORCE_FN = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double))
 
@@ -94,6 +100,18 @@ def lib():
         L.ora_fire_steps_lattice.restype = C.c_int64
         L.ora_fire_steps_lattice.argtypes = [C.POINTER(_Problem), C.POINTER(FireParams),
                                              C.POINTER(FireState), dp, dp, dp, C.c_int64, dp]
+        L.ora_descent_init.restype = None
+        L.ora_descent_init.argtypes = [C.POINTER(DescentParams), C.POINTER(FireState), C.c_int64, dp,
+                                       dp, dp, FORCE_FN, C.c_void_p, C.c_int]
+        L.ora_descent_steps.restype = C.c_int64
+        L.ora_descent_steps.argtypes = [C.POINTER(DescentParams), C.POINTER(FireState), C.c_int64,
+                                        dp, dp, dp, FORCE_FN, C.c_void_p, C.c_int64, dp]
+        L.ora_descent_init_lattice.restype = None
+        L.ora_descent_init_lattice.argtypes = [C.POINTER(_Problem), C.POINTER(DescentParams),
+                                               C.POINTER(FireState), dp, dp, dp, C.c_int]
+        L.ora_descent_steps_lattice.restype = C.c_int64
+        L.ora_descent_steps_lattice.argtypes = [C.POINTER(_Problem), C.POINTER(DescentParams),
+                                                C.POINTER(FireState), dp, dp, dp, C.c_int64, dp]
         _lib = L
     return _lib
 
@@ -113,6 +131,13 @@ def S0(A, B, C_):
     return lib().ora_S0(A, B, C_)
 
 
+def descent_params(method, dt, momentum=0.0, force_tol=1e-9, max_steps=2000) -> DescentParams:
+    """Gradient descent (method GD) or Nesterov's accelerated gradient
+    (method NESTEROV, momentum mu)."""
+    m = {"gd": GD, "nesterov": NESTEROV}.get(method, method)
+    return DescentParams(int(m), 0, float(dt), float(momentum), float(force_tol), int(max_steps))
+
+
 def fire_params(dt0=1e-3, dt_max=1e-2, alpha0=0.99, f_inc=1.1, f_dec=0.5, f_alpha=0.99,
                 n_min=5, force_tol=1e-9, max_steps=2000) -> FireParams:
     return FireParams(dt0, dt_max, alpha0, f_inc, f_dec, f_alpha, n_min, force_tol, max_steps)
@@ -127,7 +152,7 @@ class Problem:
     def __init__(self, shape, periodic=(True, True, True), A=-0.172, B=-2.12, C_=1.73,
                  L1=2.32, L2=0.0, L3=0.0, objects=(), site_records=(), object_sites=(),
                  types=None, pairs=None, fields=()):
-        """fields: (h, chi) pairs giving f_ext = -(1/3) sum chi (h.Q.h), sec. II.C
+        """fields: (h, chi) pairs giving f_ext = -(1/3) sum chi (h.Q.h), sec. II.A.3
         (chi = mu0 dchi or eps0 deps in units of |A|, h the field vector)."""
         self.shape = tuple(int(s) for s in shape)
         self.periodic = tuple(bool(p) for p in periodic)
@@ -231,6 +256,55 @@ class Problem:
         st, q, v, F = self.fire_init(params, q)
         self.fire_steps(params, st, q, v, F, params.max_steps)
         return st, q, v, F
+
+    # ---- gradient descent / Nesterov (sec. III.B) ----
+    def descent_init(self, params, q, m=None):
+        """Returns (state, q, m, F); F is the force at q (GD) or q + mu m (Nesterov)."""
+        q = self._chk(q).copy()
+        keep = m is not None
+        m = np.zeros(self.field_shape) if m is None else self._chk(m).copy()
+        F = np.empty(self.field_shape)
+        st = FireState()
+        lib().ora_descent_init_lattice(C.byref(self._s), C.byref(params), C.byref(st), _dp(q),
+                                       _dp(m), _dp(F), int(keep))
+        return st, q, m, F
+
+    def descent_steps(self, params, st, q, m, F, n_steps, trace=False):
+        tr = np.zeros((max(int(n_steps), 1), 6)) if trace else None
+        taken = lib().ora_descent_steps_lattice(C.byref(self._s), C.byref(params), C.byref(st),
+                                                _dp(q), _dp(m), _dp(F), int(n_steps),
+                                                _dp(tr) if trace else None)
+        return (taken, tr[:taken]) if trace else taken
+
+
+def descent_generic(params, x0, force, n_steps, m0=None):
+    """GD / Nesterov of the oracle over an arbitrary force(x) -> F callable.
+    Returns (state, iterates x_0..x_t, trace, m, F)."""
+    x = np.ascontiguousarray(x0, dtype=np.float64).copy()
+    n = x.size
+    m = np.zeros(n) if m0 is None else np.ascontiguousarray(m0, dtype=np.float64).copy()
+    F = np.empty(n)
+
+    def cb(ctx, xp, Fp):
+        xa = np.ctypeslib.as_array(xp, shape=(n,))
+        Fa = np.ctypeslib.as_array(Fp, shape=(n,))
+        Fa[:] = force(xa.copy())
+
+    fn = FORCE_FN(cb)
+    st = FireState()
+    lib().ora_descent_init(C.byref(params), C.byref(st), n, _dp(x), _dp(m), _dp(F), fn, None,
+                           int(m0 is not None))
+    tr = np.zeros((max(int(n_steps), 1), 6))
+    xs = [x.copy()]
+    taken = 0
+    for _ in range(int(n_steps)):
+        t = lib().ora_descent_steps(C.byref(params), C.byref(st), n, _dp(x), _dp(m), _dp(F), fn,
+                                    None, 1, _dp(tr[taken:]))
+        if t == 0:
+            break
+        taken += t
+        xs.append(x.copy())
+    return st, np.array(xs), tr[:taken], m, F
 
 
 def fire_generic(params, x0, force, n_steps, v0=None, trace=True):

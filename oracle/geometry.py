@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Shares nothing with the
 GPU library's own rasterizer; a CPU test checks that the two agree.
 
-What it encodes (paper sec. III.B, site typing; sec. II.D, anchoring):
+What it encodes (paper sec. III.B, site typing; sec. II.A.4, anchoring):
   * every site is bulk (0), boundary (1) or inside an object (2); only bulk
     and boundary sites are simulated;
   * a wall occupies one lattice plane; a sphere occupies the sites with
@@ -15,12 +15,12 @@ What it encodes (paper sec. III.B, site typing; sec. II.D, anchoring):
   * preferred director n0: nu ("normal", homeotropic), a fixed unit vector
     (oriented anchoring), or, for a patterned wall, the in-plane radial unit
     vector away from the nearest centre of a square array;
-  * preferred tensor Q0 = 3/2 S0 (n0 n0 - I/3) (sec. II.D);
+  * preferred tensor Q0 = 3/2 S0 (n0 n0 - I/3) (sec. II.A.4);
   * the strength used in W tr((Q - Q0)^2) is W for the Nobili-Durand law and
-    W / (9 S0^2) for a Rapini-Papoular strength (sec. II.D, the relation
+    W / (9 S0^2) for a Rapini-Papoular strength (sec. II.A.4, the relation
     W_RP = 9 S0^2 W_ND);
   * degenerate planar anchoring uses the Fournier-Galatola form
-    W |Qt - P Qt P|^2 with the surface normal nu (sec. II.D): law "fg" takes
+    W |Qt - P Qt P|^2 with the surface normal nu (sec. II.A.4): law "fg" takes
     W as the Fournier-Galatola strength, and a negative Rapini-Papoular
     strength (which the paper assigns to degenerate planar anchoring) enters
     as |W| / (9 S0^2).

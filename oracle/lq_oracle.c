@@ -18,8 +18,8 @@
  *     every allowed forward/backward choice per axis (sec. III.B, text after
  *     Eq. onesidedderivatives);
  *   - Nobili-Durand anchoring W tr((Q - Q0)^2) and Fournier-Galatola
- *     degenerate planar anchoring on boundary pairs (sec. II.D);
- *   - external fields, linear in Q (sec. II.C);
+ *     degenerate planar anchoring on boundary pairs (sec. II.A.4);
+ *   - external fields, linear in Q (sec. II.A.3);
  *   - forces F = -dE/dq by explicit differentiation of the discrete energy
  *     (sec. III.B, the paragraph on explicit differentiation);
  *   - FIRE, Algorithm 1 (after Bitzek et al., PRL 97, 170201 (2006)).
@@ -46,8 +46,8 @@ typedef struct {
     const double *pair_Q0; /* [n_pairs][5] preferred tensor, q components (Nobili-Durand) */
     const uint8_t *pair_kind; /* 0: Nobili-Durand, 1: Fournier-Galatola (may be NULL: all 0) */
     const double *pair_nu;    /* [n_pairs][3] surface normal (Fournier-Galatola) */
-    double S0;                /* bulk order used by Fournier-Galatola, sec. II.D */
-    double hfield[9];         /* external-field coupling: f_ext = -sum_ij Q_ij h_ij, sec. II.C */
+    double S0;                /* bulk order used by Fournier-Galatola, sec. II.A.4 */
+    double hfield[9];         /* external-field coupling: f_ext = -sum_ij Q_ij h_ij, sec. II.A.3 */
 } ora_problem;
 
 #ifdef _OPENMP
@@ -287,7 +287,7 @@ static void add_dist_grad_from(const ora_problem *p, const double *q, int64_t x,
             }
 }
 
-/* ---- anchoring of one (site, surface) pair, sec. II.D ----
+/* ---- anchoring of one (site, surface) pair, sec. II.A.4 ----
  * Nobili-Durand:      W tr((Q - Q0)^2)
  * Fournier-Galatola:  W |Qt - P Qt P|^2, Qt = Q + S0/2 I, P = I - nu nu
  * (the projector of Eq. planarDegenerate read as P_ik Qt_kl P_lj). */
@@ -349,7 +349,7 @@ static void add_pair_grad(const ora_problem *p, int64_t i, const double Q[3][3],
     }
 }
 
-/* external-field density -sum_ij Q_ij h_ij (linear in Q), sec. II.C */
+/* external-field density -sum_ij Q_ij h_ij (linear in Q), sec. II.A.3 */
 static double f_ext(const ora_problem *p, const double Q[3][3])
 {
     double t = 0.0;
@@ -570,6 +570,98 @@ int64_t ora_fire_steps(const ora_fire_params *fp, ora_fire_state *st, int64_t n,
     return taken;
 }
 
+/* ---- gradient descent and Nesterov's accelerated gradient (sec. III.C
+ * names both as alternatives to FIRE; the paper gives no formulas, so the
+ * textbook forms are taken):
+ *   GD:        q <- q + dt F(q)                     (steepest descent, i.e.
+ *              overdamped dynamics at zero temperature)
+ *   Nesterov:  m <- mu m + dt F(q + mu m);  q <- q + m
+ * The force is always kept at the point where it was last evaluated:
+ * F(q) for GD, F(y) with y = q + mu m for Nesterov, and the stop test uses
+ * the largest component of that force.  Reported per step: P = F.m,
+ * |F|, |m|, max|F| (m stays untouched by GD). ---- */
+enum { ORA_GD = 1, ORA_NESTEROV = 2 };
+
+typedef struct {
+    int32_t method;     /* ORA_GD or ORA_NESTEROV */
+    int32_t pad;
+    double dt, momentum;
+    double force_tol;
+    int64_t max_steps;
+} ora_descent_params;
+
+static void lookahead(int64_t n, const double *x, const double *m, double mu, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) y[i] = x[i] + mu * m[i];
+}
+
+static void measure(const ora_descent_params *dp, ora_fire_state *st, int64_t n, const double *m,
+                    const double *F)
+{
+    double P = 0.0, f2 = 0.0, m2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        P += F[i] * m[i];
+        f2 += F[i] * F[i];
+        m2 += m[i] * m[i];
+    }
+    st->P = P;
+    st->normF = sqrt(f2);
+    st->normv = sqrt(m2);
+    st->maxF = max_abs(n, F);
+    if (!isfinite(P) || !isfinite(f2) || !isfinite(m2) || !(st->maxF == st->maxF)) st->status = ORA_NONFINITE;
+    else if (st->maxF < dp->force_tol) st->status = ORA_CONVERGED;
+    else if (st->step >= dp->max_steps) st->status = ORA_MAX_STEPS;
+}
+
+/* m = 0 unless keep_m; F = force at q (GD) or at q + mu m (Nesterov) */
+void ora_descent_init(const ora_descent_params *dp, ora_fire_state *st, int64_t n, const double *x,
+                      double *m, double *F, ora_force_fn force, void *ctx, int keep_m)
+{
+    if (!keep_m) memset(m, 0, (size_t)n * sizeof(double));
+    if (dp->method == ORA_NESTEROV) {
+        double *y = (double *)malloc((size_t)n * sizeof(double));
+        lookahead(n, x, m, dp->momentum, y);
+        force(ctx, y, F);
+        free(y);
+    } else {
+        force(ctx, x, F);
+    }
+    memset(st, 0, sizeof(*st));
+    st->dt = dp->dt;
+    st->alpha = dp->method == ORA_NESTEROV ? dp->momentum : 0.0;
+    st->status = ORA_RUNNING;
+    measure(dp, st, n, m, F);
+}
+
+int64_t ora_descent_steps(const ora_descent_params *dp, ora_fire_state *st, int64_t n, double *x,
+                          double *m, double *F, ora_force_fn force, void *ctx, int64_t n_steps,
+                          double *trace)
+{
+    int64_t taken = 0;
+    double *y = dp->method == ORA_NESTEROV ? (double *)malloc((size_t)n * sizeof(double)) : NULL;
+    while (taken < n_steps && st->status == ORA_RUNNING) {
+        if (dp->method == ORA_NESTEROV) {
+            for (int64_t i = 0; i < n; ++i) m[i] = dp->momentum * m[i] + dp->dt * F[i];
+            for (int64_t i = 0; i < n; ++i) x[i] += m[i];
+            lookahead(n, x, m, dp->momentum, y);
+            force(ctx, y, F);
+        } else {
+            for (int64_t i = 0; i < n; ++i) x[i] += dp->dt * F[i];
+            force(ctx, x, F);
+        }
+        st->step += 1;
+        taken += 1;
+        measure(dp, st, n, m, F);
+        if (trace) {
+            double *t = trace + 6 * (taken - 1);
+            t[0] = st->P; t[1] = st->normF; t[2] = st->normv; t[3] = st->maxF; t[4] = st->dt;
+            t[5] = st->alpha;
+        }
+    }
+    free(y);
+    return taken;
+}
+
 /* lattice force as an ora_force_fn */
 static void lattice_force(void *ctx, const double *x, double *F)
 {
@@ -586,6 +678,18 @@ int64_t ora_fire_steps_lattice(const ora_problem *p, const ora_fire_params *fp, 
                                double *q, double *v, double *F, int64_t n_steps, double *trace)
 {
     return ora_fire_steps(fp, st, 5 * nsites(p), q, v, F, lattice_force, (void *)p, n_steps, trace);
+}
+
+void ora_descent_init_lattice(const ora_problem *p, const ora_descent_params *dp, ora_fire_state *st,
+                              const double *q, double *m, double *F, int keep_m)
+{
+    ora_descent_init(dp, st, 5 * nsites(p), q, m, F, lattice_force, (void *)p, keep_m);
+}
+
+int64_t ora_descent_steps_lattice(const ora_problem *p, const ora_descent_params *dp, ora_fire_state *st,
+                                  double *q, double *m, double *F, int64_t n_steps, double *trace)
+{
+    return ora_descent_steps(dp, st, 5 * nsites(p), q, m, F, lattice_force, (void *)p, n_steps, trace);
 }
 
 /* ---- per-site energy density, for sampled checks on large lattices:

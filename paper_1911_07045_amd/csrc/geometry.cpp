@@ -2,7 +2,7 @@
 // neighbour masks and per-site anchoring forms.
 //
 // Site typing follows sec. III.B (bulk, boundary, inside an object; only
-// bulk and boundary sites are simulated).  Anchoring follows sec. II.D:
+// bulk and boundary sites are simulated).  Anchoring follows sec. II.A.4:
 //   - Nobili-Durand W tr((Q - Q0)^2), Q0 = 3/2 S0 (n0 n0 - I/3); a
 //     Rapini-Papoular strength W >= 0 enters as W / (9 S0^2);
 //   - Fournier-Galatola W |Qt - P Qt P|^2, Qt = Q + S0/2 I, P = I - nu nu

@@ -4,8 +4,9 @@
 // The energy is the paper's discretization (sec. III.B): bulk Eq. (fphase),
 // distortion Eq. (fdistortionFull) (L4 = L6 = 0) from one-sided differences
 // Eq. (onesidedderivatives) averaged over every allowed forward/backward
-// choice per axis, plus Nobili-Durand anchoring (sec. II.D).  Because the
-// choices on different axes are independent, the average factorizes:
+// choice per axis, plus anchoring (sec. II.A.4) and external fields
+// (sec. II.A.3).  Because the choices on different axes are independent, the
+// average factorizes:
 //   - products of differences along one axis k average to the mean over the
 //     allowed choices of that axis, which turns the L1 term and the same-axis
 //     part of L2/L3 into bond sums, bond (x, x+e_k) weighted

@@ -220,7 +220,7 @@ def test_minimize_fg_slab_reaches_exact_planar_minimum():
 
 
 def test_minimize_bulk_in_field_reaches_field_aligned_state():
-    """Periodic bulk in a field h with chi > 0 (sec. II.C): the minimum is
+    """Periodic bulk in a field h with chi > 0 (sec. II.A.3): the minimum is
     uniaxial along h with S solving d/dS [3/4 A S^2 + 1/4 B S^3 + 9/16 C S^4
     - chi |h|^2 S / 3] = 0 near S0 (h.Q.h = S |h|^2 for n along h)."""
     say("[minimize] bulk in field")

@@ -370,7 +370,7 @@ def test_linear_field_reproduces_frank_oseen_via_paper_mapping(ora):
 
 # ---------------------------------------------------------------- anchoring
 def test_nobili_durand_reduces_to_rapini_papoular(ora):
-    """Sec. II.D: for uniaxial Q at S0, W_ND tr((Q - Q0)^2) =
+    """Sec. II.A.4: for uniaxial Q at S0, W_ND tr((Q - Q0)^2) =
     W_RP/2 (1 - (n.nu)^2) with W_RP = 9 S0^2 W_ND; a Rapini-Papoular
     strength enters through W_ND = W_RP / (9 S0^2)."""
     rng = np.random.default_rng(13)
@@ -554,7 +554,7 @@ def test_fire_at_a_stationary_point_restarts(ora):
 
 # ---------------------------------------------------------------- degenerate planar + fields
 def test_fournier_galatola_uniaxial_closed_form(ora):
-    """Sec. II.D, Eq. (planarDegenerate) with the projector P Qt P: for a
+    """Sec. II.A.4, Eq. (planarDegenerate) with the projector P Qt P: for a
     uniaxial Q at S0 with director n and a surface normal nu (c = n.nu),
     Qt - P Qt P = 3/2 S0 [c (n nu + nu n) - c^2 nu nu], so the density is
     W (9/4) S0^2 (2 c^2 - c^4): zero for every n in the surface plane, and
@@ -580,7 +580,7 @@ def test_fournier_galatola_uniaxial_closed_form(ora):
 
 
 def test_external_field_uniaxial_reduction(ora):
-    """Sec. II.C: -(1/3) chi h.Q.h at a uniaxial Q equals
+    """Sec. II.A.3: -(1/3) chi h.Q.h at a uniaxial Q equals
     -(1/2) chi S (h.n)^2 up to the n-independent chi S |h|^2 / 6."""
     rng = np.random.default_rng(32)
     h = np.array([0.3, -1.2, 0.5])
@@ -618,3 +618,111 @@ def test_forces_exact_gradient_planar_and_fields(ora, name):
     F = p.forces(q)
     Ffd = five_point_forces(p, q)
     assert np.abs(F - Ffd).max() <= 1e-10 * np.abs(F).max()
+
+
+# ---- gradient descent and Nesterov's accelerated gradient (sec. III.B) ----
+
+def _spd(rng, n):
+    X = rng.standard_normal((n, n))
+    return X @ X.T / n + 0.2 * np.eye(n)
+
+
+def test_gradient_descent_on_a_quadratic_is_the_matrix_power(ora):
+    """For E = 1/2 x^T H x, GD gives x_t = (I - dt H)^t x_0: in the eigenbasis
+    of H each coordinate is multiplied by (1 - dt lambda) per step."""
+    rng = np.random.default_rng(51)
+    H = _spd(rng, 7)
+    x0 = rng.standard_normal(7)
+    dt = 0.3
+    st, xs, tr, m, F = ora.descent_generic(ora.descent_params("gd", dt, force_tol=0.0, max_steps=100),
+                                           x0, lambda x: -H @ x, 25)
+    lam, U = np.linalg.eigh(H)
+    for t in (1, 7, 25):
+        ref = U @ ((1.0 - dt * lam) ** t * (U.T @ x0))
+        assert np.abs(xs[t] - ref).max() <= 1e-13 * np.abs(x0).max()
+    assert np.allclose(F, -H @ xs[-1], rtol=0, atol=1e-15)
+    assert st.step == 25 and np.all(m == 0.0)
+
+
+def test_nesterov_on_a_quadratic_follows_its_two_term_recurrence(ora):
+    """For E = 1/2 x^T H x, Nesterov's m' = mu m + dt F(x + mu m), x' = x + m'
+    acts on each eigen-coordinate (x, m) of H through the 2x2 matrix
+    [[1 - dt l, mu (1 - dt l)], [-dt l, mu (1 - dt l)]]; the t-th iterate is
+    its t-th power applied to (x_0, 0)."""
+    rng = np.random.default_rng(52)
+    H = _spd(rng, 6)
+    x0 = rng.standard_normal(6)
+    dt, mu = 0.25, 0.8
+    st, xs, tr, m, F = ora.descent_generic(
+        ora.descent_params("nesterov", dt, mu, force_tol=0.0, max_steps=100), x0, lambda x: -H @ x, 40)
+    lam, U = np.linalg.eigh(H)
+    c0 = U.T @ x0
+    for t in (1, 2, 13, 40):
+        xe = np.empty(6)
+        for i, l in enumerate(lam):
+            a = 1.0 - dt * l
+            T = np.array([[a, mu * a], [-dt * l, mu * a]])
+            xe[i] = (np.linalg.matrix_power(T, t) @ np.array([c0[i], 0.0]))[0]
+        assert np.abs(xs[t] - U @ xe).max() <= 1e-12 * np.abs(x0).max()
+    # the kept force is the one at the look-ahead point, and P = F.m
+    assert np.allclose(F, -H @ (xs[-1] + mu * m), rtol=0, atol=1e-14)
+    assert tr[-1, 0] == pytest.approx(F @ m, rel=1e-12)
+    assert tr[-1, 5] == mu and tr[-1, 4] == dt
+
+
+def test_nesterov_without_momentum_is_gradient_descent_bitwise(ora):
+    p = ora.Problem((6, 5, 4), L1=2.32, L2=1.16, L3=0.7, objects=[
+        dict(kind="wall", axis=2, plane=0, law="fg", W=0.8),
+        dict(kind="sphere", center=(2.5, 2.0, 2.0), radius=1.2, law="nd", W=1.0, dir="normal")],
+        fields=[((0.3, 0.4, 0.1), 0.5)])
+    q0 = p.uniaxial(synth.random_directors(53, p.N))
+    out = []
+    for method in ("gd", "nesterov"):
+        prm = ora.descent_params(method, 0.02, 0.0, force_tol=0.0, max_steps=100)
+        st, q, m, F = p.descent_init(prm, q0)
+        p.descent_steps(prm, st, q, m, F, 30)
+        out.append((q, F))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_gradient_descent_decreases_the_lattice_energy(ora):
+    """A small GD step changes the energy by -dt |F|^2 to first order, and
+    the energy decreases monotonically along the descent."""
+    p = ora.Problem((7, 6, 5), (True, True, False), L1=2.32, L2=1.16, L3=1.16, objects=[
+        dict(kind="wall", axis=2, plane=0, law="rp", W=-2.0),
+        dict(kind="wall", axis=2, plane=4, law="nd", W=0.6, dir=(1.0, 0.0, 0.0))],
+        fields=[((0.0, 1.0, 0.0), 0.4)])
+    q0 = p.uniaxial(synth.random_directors(54, p.N))
+    F0 = p.forces(q0)
+    err = []
+    for dt in (1e-4, 1e-5):
+        prm = ora.descent_params("gd", dt, force_tol=0.0, max_steps=10)
+        st, q, m, F = p.descent_init(prm, q0)
+        p.descent_steps(prm, st, q, m, F, 1)
+        err.append(abs((p.energy(q) - p.energy(q0)) / (-dt * (F0 * F0).sum()) - 1.0))
+    # the second-order remainder shrinks with dt
+    assert err[0] < 0.05 and 0.05 < err[1] / err[0] < 0.2
+    prm = ora.descent_params("gd", 0.005, force_tol=0.0, max_steps=1000)
+    st, q, m, F = p.descent_init(prm, q0)
+    E = [p.energy(q)]
+    for _ in range(40):
+        p.descent_steps(prm, st, q, m, F, 5)
+        E.append(p.energy(q))
+    assert all(b < a for a, b in zip(E, E[1:]))
+
+
+def test_descent_stop_tests(ora):
+    """Stops with CONVERGED on the step where max|F| first drops below the
+    tolerance, with MAX_STEPS at the step limit, and at once when the
+    initial state already satisfies the tolerance."""
+    H = np.diag([1.0, 0.5])
+    f = lambda x: -H @ x
+    st, xs, tr, m, F = ora.descent_generic(ora.descent_params("gd", 0.5, force_tol=1e-3, max_steps=1000),
+                                           [1.0, 1.0], f, 1000)
+    maxF = np.abs(tr[:, 3])
+    assert st.status == ora.CONVERGED and maxF[-1] < 1e-3 and np.all(maxF[:-1] >= 1e-3)
+    st, xs, tr, m, F = ora.descent_generic(ora.descent_params("nesterov", 0.5, 0.5, force_tol=0.0,
+                                                              max_steps=17), [1.0, 1.0], f, 1000)
+    assert st.status == ora.MAX_STEPS and st.step == 17 and len(xs) == 18
+    st, xs, tr, m, F = ora.descent_generic(ora.descent_params("gd", 0.5, force_tol=10.0), [1.0, 1.0], f, 5)
+    assert st.status == ora.CONVERGED and st.step == 0 and len(xs) == 1
