@@ -106,6 +106,60 @@ def gpu_leg(cfg, steps, warmup):
                 ws_bytes=lat.workspace_bytes())
 
 
+def _timed_steps(lat, steps):
+    """Wall seconds and per-step kernel milliseconds (HIP events on the
+    library's stream, minus a zero-step call) of lat.fire_step(steps)."""
+    import torch
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(lat.stream)
+    rep = lat.fire_step(steps)
+    ev[1].record(lat.stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ev[2].record(lat.stream)
+    lat.fire_step(0)
+    ev[3].record(lat.stream)
+    torch.cuda.synchronize()
+    kernel_ms = max(ev[0].elapsed_time(ev[1]) - ev[2].elapsed_time(ev[3]), 1e-9) / steps
+    return t1 - t0, kernel_ms, rep
+
+
+def minimizer_leg(cfg, steps=300, warmup=20):
+    """Gradient descent and Nesterov steps on the same workload: the fused
+    kernel moves q and F (GD: 20 values per site) or q, m and F (Nesterov:
+    30 values per site)."""
+    import numpy as np
+    import torch
+
+    from paper_1911_07045_amd import lqfire, synth
+
+    nx, ny, nz = cfg["shape"]
+    N = nx * ny * nz
+    elem = 8 if cfg["prec"] == "f64" else 4
+    out = {}
+    for method, dt, mu, vals in (("gd", 0.01, 0.0, 20), ("nesterov", 0.01, 0.9, 30)):
+        lat = lqfire.lattice_from_config(cfg)
+        dirs = torch.from_numpy(np.ascontiguousarray(synth.random_directors(cfg["dir_seed"], N))).cuda()
+        q = lat.set_uniaxial(dirs, lat.empty())
+        del dirs
+        v, F = lat.empty(), lat.empty()
+        lat.descent_init(lqfire.make_descent_params(method, dt, mu, force_tol=0.0, max_steps=1 << 62), q, v, F)
+        lat.fire_step(warmup)
+        wall, kernel_ms, rep = _timed_steps(lat, steps)
+        assert rep.status == lqfire.RUNNING, rep.as_dict()
+        gbs = vals * elem * N / (kernel_ms * 1e-3) / 1e9
+        out[method] = {"dt": dt, "momentum": mu, "steps": steps, "ms_per_step": 1e3 * wall / steps,
+                       "kernel_ms": kernel_ms, "site_updates_per_s": N * steps / wall,
+                       "algorithmic_bytes_per_site": vals * elem, "achieved_GBs": gbs,
+                       "frac_hbm_peak": gbs / HBM_PEAK_GBS}
+        del q, v, F
+        lat.close()
+    return out
+
+
 def cpu_leg(cfg):
     """The FP64 oracle on the same workload: FIRE initialisation untimed,
     then whole FIRE steps over the full lattice until about 10 s have passed."""
@@ -226,6 +280,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--no-minimizers", action="store_true",
+                    help="skip the gradient-descent / Nesterov step timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of a known size (HBM counter scale)")
     args = ap.parse_args()
@@ -268,6 +324,9 @@ def main():
     if not args.no_precision and cfg["prec"] == "f32":
         print("[bench] precision form", file=sys.stderr, flush=True)
         out["precision"] = precision_leg(cfg)
+    if not args.no_minimizers:
+        print("[bench] gradient descent / Nesterov steps", file=sys.stderr, flush=True)
+        out["minimizers"] = minimizer_leg(cfg)
     if not args.no_serving:
         print("[bench] serving stream", file=sys.stderr, flush=True)
         out["serving"] = serving_leg(args.serving_requests)

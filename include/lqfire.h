@@ -210,8 +210,9 @@ int64_t lq_workspace_bytes(const lq_lattice* lat);
 int lq_fire_init(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F,
                  void* workspace, int64_t workspace_bytes, const lq_fire_report* resume);
 
-/* Runs up to n_steps FIRE steps on the device with no host round trip
- * between steps, stopping early on convergence, max_steps or a non-finite
+/* Runs up to n_steps steps of the bound minimizer (FIRE, or the descent
+ * bound by lq_descent_init) on the device with no host round trip between
+ * steps, stopping early on convergence, max_steps or a non-finite
  * reduction.  On return the bound q, v, F hold the state after the last step
  * (v after steering), and *out the controller.  LQ_ENONFINITE when the run
  * hit a non-finite reduction. */
@@ -221,6 +222,41 @@ int lq_fire_step(lq_lattice* lat, int64_t n_steps, lq_fire_report* out);
 int lq_minimize(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F,
                 void* workspace, int64_t workspace_bytes, lq_fire_report* out);
 
+/* ---- gradient descent and Nesterov's accelerated gradient ----
+ * The alternatives to FIRE that sec. III.B names (steepest descent, and
+ * Nesterov's momentum method of the GUI).  The paper gives no formulas; the
+ * textbook forms are used, with a fixed step dt:
+ *   LQ_METHOD_GD:        q <- q + dt F(q)
+ *   LQ_METHOD_NESTEROV:  m <- mu m + dt F(q + mu m),  q <- q + m
+ * Nesterov keeps m in the v buffer and F at the look-ahead point q + mu m;
+ * GD leaves v untouched.  Both run through the same fused kernel as FIRE
+ * and are advanced by lq_fire_step, whose report then carries dt, alpha =
+ * mu (0 for GD), P = F.m, normv = |m| and n_pos = restarts = 0. */
+#define LQ_METHOD_FIRE 0
+#define LQ_METHOD_GD 1
+#define LQ_METHOD_NESTEROV 2
+
+typedef struct {
+    int32_t method;    /* LQ_METHOD_GD or LQ_METHOD_NESTEROV */
+    int32_t pad;
+    double dt;         /* step, > 0 */
+    double momentum;   /* Nesterov mu, 0 <= mu < 1 (ignored by GD) */
+    double force_tol;  /* converged when max |F_i| < force_tol */
+    int64_t max_steps; /* stop after this many steps since initialization */
+} lq_descent_params;
+
+/* Binds q, v, F and the workspace (lq_workspace_bytes) like lq_fire_init and
+ * starts the descent: resume == NULL sets v = 0 (Nesterov) and the step
+ * count to 0; resume != NULL keeps v and takes the step count from *resume.
+ * F = F(q) for GD, F(q + mu v) for Nesterov.  LQ_EINVAL on bad parameters;
+ * LQ_ENONFINITE when the initial forces are not finite. */
+int lq_descent_init(lq_lattice* lat, const lq_descent_params* dp, void* q, void* v, void* F,
+                    void* workspace, int64_t workspace_bytes, const lq_fire_report* resume);
+
+/* lq_descent_init (fresh) + lq_fire_step until converged or max_steps. */
+int lq_descent_minimize(lq_lattice* lat, const lq_descent_params* dp, void* q, void* v, void* F,
+                        void* workspace, int64_t workspace_bytes, lq_fire_report* out);
+
 /* ---- batched FIRE for many small lattices (continuous batching) ----
  * A batch advances all its member lattices by one FIRE step per kernel
  * launch; every member keeps its own controller, partial sums and stop test,
@@ -228,7 +264,8 @@ int lq_minimize(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, voi
  * lq_fire_step would give it alone.  Members are added and removed between
  * lq_batch_step calls, which is how a serving loop admits and retires
  * requests while others keep running.  All members of a batch share prec
- * and whether L2/L3 are in use, and live on the batch's device. */
+ * and whether L2/L3 are in use, run FIRE (lq_fire_init), and live on the
+ * batch's device. */
 typedef struct lq_batch lq_batch;
 
 /* capacity: maximum number of members (1 .. 65536).  stream: hipStream_t or

@@ -36,8 +36,9 @@ struct lq_lattice {
     EnergyOut* d_eout = nullptr;
     uint32_t* d_eticket = nullptr;
     EnergyOut* h_eout = nullptr;  // pinned
-    // FIRE binding
+    // minimizer binding
     bool bound = false;
+    int method = LQ_METHOD_FIRE;
     void* q = nullptr;
     void* v = nullptr;
     void* F = nullptr;
@@ -411,12 +412,10 @@ static int check_fire_params(lq_lattice* lat, const lq_fire_params* fp) {
     return LQ_OK;
 }
 
-int lq_fire_init(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F, void* workspace,
-                 int64_t workspace_bytes, const lq_fire_report* resume) {
-    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
-    lat->bound = false;
-    int rc = check_fire_params(lat, fp);
-    if (rc == LQ_OK) rc = check_dev_ptr(lat, q, "q");
+// Checks and binds q, v, F and the workspace (ping-pong buffers, partials,
+// device state).  Leaves the lattice unbound.
+static int bind_buffers(lq_lattice* lat, void* q, void* v, void* F, void* workspace, int64_t workspace_bytes) {
+    int rc = check_dev_ptr(lat, q, "q");
     if (rc == LQ_OK) rc = check_dev_ptr(lat, v, "v");
     if (rc == LQ_OK) rc = check_dev_ptr(lat, F, "F");
     if (rc == LQ_OK) rc = check_dev_ptr(lat, workspace, "workspace");
@@ -425,12 +424,6 @@ int lq_fire_init(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, vo
     if (workspace_bytes < lq_workspace_bytes(lat))
         return fail(lat, LQ_ENOMEM, "workspace smaller than lq_workspace_bytes()");
     if (((uintptr_t)workspace & 255) != 0) return fail(lat, LQ_EINVAL, "workspace must be 256-byte aligned");
-    if (resume) {
-        if (!(resume->dt > 0.0) || !std::isfinite(resume->dt) || !(resume->alpha >= 0.0) ||
-            !(resume->alpha <= 1.0) || resume->step < 0 || resume->n_pos < 0 || resume->restarts < 0)
-            return fail(lat, LQ_EINVAL, "bad resume state");
-    }
-    HIPCHK(lat, hipSetDevice(lat->device));
     const int64_t field = align256(5 * lat->N * (int64_t)elem_size(lat));
     char* ws = (char*)workspace;
     void* q1 = ws;
@@ -443,7 +436,38 @@ int lq_fire_init(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, vo
     lat->F = F;
     lat->b64 = Bufs<double>{{(double*)q, (double*)q1}, {(double*)v, (double*)v1}, {(double*)F, (double*)F1}};
     lat->b32 = Bufs<float>{{(float*)q, (float*)q1}, {(float*)v, (float*)v1}, {(float*)F, (float*)F1}};
+    return LQ_OK;
+}
 
+// Uploads the host controller, runs the initial reduction (with v, or
+// without when v_red is NULL) and binds the lattice.
+static int start_controller(lq_lattice* lat, FireDev& s, const void* v_red) {
+    HIPCHK(lat, hipMemcpyAsync(lat->d_state, &s, sizeof(FireDev), hipMemcpyHostToDevice, lat->stream));
+    int rc = launch_fire_init_reduce(lat->dev, lat->p.prec, lat->F, v_red, lat->d_partials, lat->d_state,
+                                     lat->stream);
+    if (rc != LQ_OK) return fail(lat, rc, "kernel launch failed");
+    HIPCHK(lat, hipMemcpyAsync(lat->h_state, lat->d_state, sizeof(FireDev), hipMemcpyDeviceToHost, lat->stream));
+    HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    lat->bound = true;
+    if (lat->h_state->status == LQ_NONFINITE) return fail(lat, LQ_ENONFINITE, "initial forces are not finite");
+    return LQ_OK;
+}
+
+int lq_fire_init(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F, void* workspace,
+                 int64_t workspace_bytes, const lq_fire_report* resume) {
+    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
+    lat->bound = false;
+    int rc = check_fire_params(lat, fp);
+    if (rc != LQ_OK) return rc;
+    if (resume) {
+        if (!(resume->dt > 0.0) || !std::isfinite(resume->dt) || !(resume->alpha >= 0.0) ||
+            !(resume->alpha <= 1.0) || resume->step < 0 || resume->n_pos < 0 || resume->restarts < 0)
+            return fail(lat, LQ_EINVAL, "bad resume state");
+    }
+    HIPCHK(lat, hipSetDevice(lat->device));
+    rc = bind_buffers(lat, q, v, F, workspace, workspace_bytes);
+    if (rc != LQ_OK) return rc;
+    lat->method = LQ_METHOD_FIRE;
     rc = launch_forces(lat->dev, lat->l23, lat->p.prec, q, F, lat->stream);
     if (rc == LQ_OK && !resume) rc = launch_fill_zero(v, 5 * lat->N * (int64_t)elem_size(lat), lat->stream);
     if (rc != LQ_OK) return fail(lat, rc, "kernel launch failed");
@@ -470,14 +494,53 @@ int lq_fire_init(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, vo
     s.n_min = fp->n_min;
     s.max_steps = fp->max_steps;
     s.ticket = 0;
-    HIPCHK(lat, hipMemcpyAsync(lat->d_state, &s, sizeof(FireDev), hipMemcpyHostToDevice, lat->stream));
-    rc = launch_fire_init_reduce(lat->dev, lat->p.prec, F, v, lat->d_partials, lat->d_state, lat->stream);
+    s.method = LQ_METHOD_FIRE;
+    return start_controller(lat, s, v);
+}
+
+int lq_descent_init(lq_lattice* lat, const lq_descent_params* dp, void* q, void* v, void* F, void* workspace,
+                    int64_t workspace_bytes, const lq_fire_report* resume) {
+    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
+    lat->bound = false;
+    if (!dp) return fail(lat, LQ_EINVAL, "descent params is NULL");
+    if (dp->method != LQ_METHOD_GD && dp->method != LQ_METHOD_NESTEROV)
+        return fail(lat, LQ_EINVAL, "method must be LQ_METHOD_GD or LQ_METHOD_NESTEROV");
+    if (!std::isfinite(dp->dt) || !(dp->dt > 0.0) || !std::isfinite(dp->force_tol) || dp->force_tol < 0.0 ||
+        dp->max_steps < 0)
+        return fail(lat, LQ_EINVAL, "descent parameter out of range");
+    const bool nag = dp->method == LQ_METHOD_NESTEROV;
+    if (nag && !(dp->momentum >= 0.0 && dp->momentum < 1.0))
+        return fail(lat, LQ_EINVAL, "Nesterov momentum must lie in [0, 1)");
+    if (resume && resume->step < 0) return fail(lat, LQ_EINVAL, "bad resume state");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    int rc = bind_buffers(lat, q, v, F, workspace, workspace_bytes);
+    if (rc != LQ_OK) return rc;
+    lat->method = dp->method;
+    if (nag && resume) {
+        // force at the look-ahead point, built in the spare q buffer
+        void* y = lat->p.prec == LQ_F64 ? (void*)lat->b64.q[1] : (void*)lat->b32.q[1];
+        rc = launch_lookahead(lat->dev, lat->p.prec, q, v, dp->momentum, y, lat->stream);
+        if (rc == LQ_OK) rc = launch_forces(lat->dev, lat->l23, lat->p.prec, y, F, lat->stream);
+    } else {
+        rc = launch_forces(lat->dev, lat->l23, lat->p.prec, q, F, lat->stream);
+        if (rc == LQ_OK && nag) rc = launch_fill_zero(v, 5 * lat->N * (int64_t)elem_size(lat), lat->stream);
+    }
     if (rc != LQ_OK) return fail(lat, rc, "kernel launch failed");
-    HIPCHK(lat, hipMemcpyAsync(lat->h_state, lat->d_state, sizeof(FireDev), hipMemcpyDeviceToHost, lat->stream));
-    HIPCHK(lat, hipStreamSynchronize(lat->stream));
-    lat->bound = true;
-    if (lat->h_state->status == LQ_NONFINITE) return fail(lat, LQ_ENONFINITE, "initial forces are not finite");
-    return LQ_OK;
+    FireDev& s = *lat->h_state;
+    std::memset(&s, 0, sizeof(FireDev));
+    s.dt = dp->dt;
+    s.alpha = nag ? dp->momentum : 0.0;
+    s.mu = nag ? dp->momentum : 0.0;
+    s.method = dp->method;
+    s.c_v = 1.0;
+    s.c_F = 0.0;
+    s.step = resume ? resume->step : 0;
+    s.stop_at = s.step;
+    s.status = LQ_RUNNING;
+    s.init_pending = 1;
+    s.tol = dp->force_tol;
+    s.max_steps = dp->max_steps;
+    return start_controller(lat, s, nag ? v : nullptr);
 }
 
 static void fill_report(const FireDev& s, lq_fire_report* out) {
@@ -497,19 +560,20 @@ static void fill_report(const FireDev& s, lq_fire_report* out) {
 
 int lq_fire_step(lq_lattice* lat, int64_t n_steps, lq_fire_report* out) {
     if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
-    if (!lat->bound) return fail(lat, LQ_ESTATE, "lq_fire_init has not bound buffers to this lattice");
+    if (!lat->bound) return fail(lat, LQ_ESTATE, "no minimizer is bound to this lattice");
     if (n_steps < 0) return fail(lat, LQ_EINVAL, "n_steps < 0");
     HIPCHK(lat, hipSetDevice(lat->device));
     const void* bufs = lat->p.prec == LQ_F64 ? (const void*)&lat->b64 : (const void*)&lat->b32;
     int rc = launch_begin(lat->d_state, n_steps, lat->stream);
-    if (rc == LQ_OK) rc = launch_fire_steps(lat->dev, lat->l23, lat->p.prec, bufs, lat->d_partials, lat->d_state,
-                                            n_steps, lat->stream);
-    if (rc == LQ_OK) rc = launch_finalize(lat->dev, lat->p.prec, bufs, lat->d_state, lat->stream);
+    if (rc == LQ_OK) rc = launch_fire_steps(lat->dev, lat->l23, lat->p.prec, lat->method, bufs, lat->d_partials,
+                                            lat->d_state, n_steps, lat->stream);
+    if (rc == LQ_OK)
+        rc = launch_finalize(lat->dev, lat->p.prec, lat->method != LQ_METHOD_GD, bufs, lat->d_state, lat->stream);
     if (rc != LQ_OK) return fail(lat, rc, "kernel launch failed");
     HIPCHK(lat, hipMemcpyAsync(lat->h_state, lat->d_state, sizeof(FireDev), hipMemcpyDeviceToHost, lat->stream));
     HIPCHK(lat, hipStreamSynchronize(lat->stream));
     fill_report(*lat->h_state, out);
-    if (lat->h_state->status == LQ_NONFINITE) return fail(lat, LQ_ENONFINITE, "a FIRE reduction is not finite");
+    if (lat->h_state->status == LQ_NONFINITE) return fail(lat, LQ_ENONFINITE, "a step reduction is not finite");
     return LQ_OK;
 }
 
@@ -522,6 +586,22 @@ int lq_minimize(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, voi
     int64_t chunk = 64;
     while (r.status == LQ_RUNNING) {
         rc = lq_fire_step(lat, std::min<int64_t>(chunk, fp->max_steps - r.step), &r);
+        if (rc != LQ_OK) break;
+        chunk = std::min<int64_t>(chunk * 2, 1024);
+    }
+    if (out) *out = r;
+    return rc;
+}
+
+int lq_descent_minimize(lq_lattice* lat, const lq_descent_params* dp, void* q, void* v, void* F, void* workspace,
+                        int64_t workspace_bytes, lq_fire_report* out) {
+    int rc = lq_descent_init(lat, dp, q, v, F, workspace, workspace_bytes, nullptr);
+    if (rc != LQ_OK) return rc;
+    lq_fire_report r{};
+    fill_report(*lat->h_state, &r);
+    int64_t chunk = 64;
+    while (r.status == LQ_RUNNING) {
+        rc = lq_fire_step(lat, std::min<int64_t>(chunk, dp->max_steps - r.step), &r);
         if (rc != LQ_OK) break;
         chunk = std::min<int64_t>(chunk * 2, 1024);
     }
@@ -604,6 +684,7 @@ int32_t lq_batch_size(const lq_batch* b) { return b ? (int32_t)b->members.size()
 int lq_batch_add(lq_batch* b, lq_lattice* lat) {
     if (!b || !lat) return fail(lat, LQ_EINVAL, "batch or lattice is NULL");
     if (!lat->bound) return fail(lat, LQ_ESTATE, "lattice is not bound by lq_fire_init");
+    if (lat->method != LQ_METHOD_FIRE) return fail(lat, LQ_EINVAL, "batched stepping runs FIRE only");
     if ((int)b->members.size() >= b->capacity) return fail(lat, LQ_EINVAL, "batch is full");
     if (lat->device != b->device) return fail(lat, LQ_EINVAL, "lattice and batch are on different devices");
     for (lq_lattice* m : b->members)

@@ -414,7 +414,9 @@ __device__ void fire_control(FireDev* st, double P, double nF2, double nv2, doub
         st->c_v = 1.0; st->c_F = 0.0;
         return;
     }
-    if (P > 0.0) {
+    if (st->method != LQ_METHOD_FIRE) {
+        // gradient descent and Nesterov: fixed dt and momentum, no steering
+    } else if (P > 0.0) {
         double nF = sqrt(nF2), nv = sqrt(nv2);
         st->c_v = 1.0 - st->alpha;
         st->c_F = st->alpha * nv / nF;
@@ -469,8 +471,14 @@ __device__ void grid_finish(double r[4], double* partials, FireDev* st, int nblo
 }
 
 // ---------------------------------------------------------------------------
-// The z-marching kernel.  STEP = false: F = force(q) only.  STEP = true: one
-// fused FIRE step between the two buffers of b.
+// The z-marching kernel.  MODE_FORCE: F = force(q) only.  MODE_FIRE,
+// MODE_GD, MODE_NAG: one fused minimizer step between the two buffers of b:
+//   FIRE      v1 = c_v v + c_F F + dt/2 F, q' = q + dt v1, F' = F(q'),
+//             v' = v1 + dt/2 F'   (Algorithm 1, steering of the previous step
+//             applied first);
+//   GD        q' = q + dt F, F' = F(q');
+//   Nesterov  m' = mu m + dt F, q' = q + m', F' = F(q' + mu m')  (m in the
+//             v buffers; the stencil holds the look-ahead point q' + mu m').
 //
 // A block owns a TX x TY column tile and the planes z0 .. z0+zc-1.  Plane i
 // of the march (global z = z0 - 1 + i, i = 0 .. zc+1) is loaded into
@@ -490,7 +498,7 @@ __device__ __forceinline__ void ring_pos(int r, int& px, int& py) {
     else { px = PX - 1; py = r - 2 * PX - (PY - 2) + 1; }
 }
 
-template <typename T, bool L23, bool STEP, bool BULK>
+template <typename T, bool L23, int MODE, bool BULK>
 __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_in,
                                       const T* __restrict__ v_in, const T* __restrict__ F_in,
                                       T* __restrict__ q_out, T* __restrict__ v_out,
@@ -498,6 +506,8 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                                       int z0, int zc, T (*sq)[5][PY][PX], uint8_t (*sm)[PY][PX],
                                       double red[4]) {
     constexpr int NS = 4;
+    constexpr bool STEP = MODE != MODE_FORCE;
+    constexpr bool USES_V = MODE == MODE_FIRE || MODE == MODE_NAG;
     const int64_t N = L.N;
     const int nxy = L.nx * L.ny;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
@@ -530,10 +540,10 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
     const uint32_t cs = (uint32_t)N * (uint32_t)sizeof(T);  // bytes per component
     const uint32_t fb = 5u * cs;                               // bytes per field
     const __amdgpu_buffer_rsrc_t rq_in = field_rsrc(q_in, fb);
-    const __amdgpu_buffer_rsrc_t rv_in = field_rsrc(STEP ? v_in : q_in, fb);
+    const __amdgpu_buffer_rsrc_t rv_in = field_rsrc(USES_V ? v_in : q_in, fb);
     const __amdgpu_buffer_rsrc_t rF_in = field_rsrc(STEP ? F_in : q_in, fb);
     const __amdgpu_buffer_rsrc_t rq_out = field_rsrc(STEP ? q_out : F_out, fb);
-    const __amdgpu_buffer_rsrc_t rv_out = field_rsrc(STEP ? v_out : F_out, fb);
+    const __amdgpu_buffer_rsrc_t rv_out = field_rsrc(USES_V ? v_out : F_out, fb);
     const __amdgpu_buffer_rsrc_t rF_out = field_rsrc(F_out, fb);
     const __amdgpu_buffer_rsrc_t rmask = field_rsrc(L.mask, (uint32_t)N);
     constexpr uint32_t NONE = 0xFFFFFFFFu;  // past every resource: loads give 0, stores drop
@@ -548,7 +558,8 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             rq[c] = bld<T>(rq_in, off, c * cs);
-            if (STEP) { rv[c] = bld<T>(rv_in, off, c * cs); rf[c] = bld<T>(rF_in, off, c * cs); }
+            if (USES_V) rv[c] = bld<T>(rv_in, off, c * cs);
+            if (STEP) rf[c] = bld<T>(rF_in, off, c * cs);
         }
         if (!BULK) rm = __builtin_amdgcn_raw_buffer_load_b8(rmask, (int)(ok ? site : NONE), 0, 0);
 #pragma unroll
@@ -557,23 +568,36 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
             const uint32_t t = (uint32_t)(it_sxy[j] + nxy * wz);
             const uint32_t offj = okj ? ((uint32_t)it_c[j] * (uint32_t)N + t) * (uint32_t)sizeof(T) : NONE;
             iq[j] = bld<T>(rq_in, offj, 0u);
-            if (STEP) { iv[j] = bld<T>(rv_in, offj, 0u); iF[j] = bld<T>(rF_in, offj, 0u); }
+            if (USES_V) iv[j] = bld<T>(rv_in, offj, 0u);
+            if (STEP) iF[j] = bld<T>(rF_in, offj, 0u);
             if (!BULK) im[j] = __builtin_amdgcn_raw_buffer_load_b8(rmask, (int)(okj && it_c[j] == 0 ? t : NONE), 0, 0);
         }
     };
     // drift the registers into LDS slot; returns the own site's q' and v1
+    // (FIRE: v after the first half kick; Nesterov: m')
     auto drift = [&](int slot, T qn[5], T v1[5], uint32_t& m) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            if (STEP) {
+            T x;
+            if (MODE == MODE_FIRE) {
                 const T vm = fma_t(cv, rv[c], cF * rf[c]);
                 v1[c] = fma_t(hdt, rf[c], vm);
                 qn[c] = fma_t(dt, v1[c], rq[c]);
+                x = qn[c];
+            } else if (MODE == MODE_GD) {
+                qn[c] = fma_t(dt, rf[c], rq[c]);
+                v1[c] = T(0);
+                x = qn[c];
+            } else if (MODE == MODE_NAG) {
+                v1[c] = fma_t(cv, rv[c], dt * rf[c]);
+                qn[c] = rq[c] + v1[c];
+                x = fma_t(cv, v1[c], qn[c]);
             } else {
                 qn[c] = rq[c];
                 v1[c] = T(0);
+                x = qn[c];
             }
-            sq[slot][c][ty + 1][tx + 1] = qn[c];
+            sq[slot][c][ty + 1][tx + 1] = x;
         }
         m = BULK ? (uint32_t)M_FULL : rm;
         if (!BULK) sm[slot][ty + 1][tx + 1] = (uint8_t)rm;
@@ -581,9 +605,14 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
         for (int j = 0; j < ITEMS_PER_THREAD; ++j) {
             if (it_c[j] < 0) continue;
             T x = iq[j];
-            if (STEP) {
+            if (MODE == MODE_FIRE) {
                 const T vm = fma_t(cv, iv[j], cF * iF[j]);
                 x = fma_t(dt, fma_t(hdt, iF[j], vm), x);
+            } else if (MODE == MODE_GD) {
+                x = fma_t(dt, iF[j], x);
+            } else if (MODE == MODE_NAG) {
+                const T mj = fma_t(cv, iv[j], dt * iF[j]);
+                x = fma_t(cv, mj, x + mj);
             }
             sq[slot][it_c[j]][it_py[j]][it_px[j]] = x;
             if (!BULK && it_c[j] == 0) sm[slot][it_py[j]][it_px[j]] = (uint8_t)im[j];
@@ -601,24 +630,25 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
     // 1 .. zc are stored nowhere.
     // v1 and mask of the own site: `older` is the plane whose force is
     // evaluated in this iteration, `newer` the plane just drifted.
-    T v1_older[5], v1_newer[5], q_unused[5];
+    T v1_older[5], v1_newer[5], q_older[5], q_newer[5];
     uint32_t m_older = 0, m_newer = 0;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) { v1_older[c] = T(0); v1_newer[c] = T(0); }
+    for (int c = 0; c < 5; ++c) { v1_older[c] = T(0); v1_newer[c] = T(0); q_older[c] = T(0); q_newer[c] = T(0); }
     load(0);
     __builtin_amdgcn_sched_barrier(0);  // keep the dropped stores behind the loads
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
         bst<T>(rF_out, NONE, c * cs, T(0));
-        if (STEP) { bst<T>(rq_out, NONE, c * cs, T(0)); bst<T>(rv_out, NONE, c * cs, T(0)); }
+        if (STEP) bst<T>(rq_out, NONE, c * cs, T(0));
+        if (USES_V) bst<T>(rv_out, NONE, c * cs, T(0));
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma clang loop unroll(disable)
     for (int j = 0; j <= zc + 1; ++j) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) v1_older[c] = v1_newer[c];
+        for (int c = 0; c < 5; ++c) { v1_older[c] = v1_newer[c]; q_older[c] = q_newer[c]; }
         m_older = m_newer;
-        drift(slot_of(j), q_unused, v1_newer, m_newer);
+        drift(slot_of(j), q_newer, v1_newer, m_newer);
         __builtin_amdgcn_sched_barrier(0);
         load(j + 1);
         __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of this plane's stores
@@ -638,9 +668,9 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 const T Fc = live ? F[c] : T(0);
-                if (STEP) {
-                    const T v2 = live ? fma_t(hdt, F[c], v1_older[c]) : T(0);
-                    const T qc = live ? P.at(0, 0, 0, c) : T(0);
+                if (MODE == MODE_FIRE || MODE == MODE_NAG) {
+                    const T v2 = live ? (MODE == MODE_FIRE ? fma_t(hdt, F[c], v1_older[c]) : v1_older[c]) : T(0);
+                    const T qc = live ? (MODE == MODE_FIRE ? P.at(0, 0, 0, c) : q_older[c]) : T(0);
                     bst<T>(rq_out, off, c * cs, qc);
                     bst<T>(rv_out, off, c * cs, v2);
                     bst<T>(rF_out, off, c * cs, Fc);
@@ -648,6 +678,13 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                     red[0] = fma(fd, vd, red[0]);
                     red[1] = fma(fd, fd, red[1]);
                     red[2] = fma(vd, vd, red[2]);
+                    red[3] = fmax(red[3], fabs(fd));
+                } else if (MODE == MODE_GD) {
+                    const T qc = live ? P.at(0, 0, 0, c) : T(0);
+                    bst<T>(rq_out, off, c * cs, qc);
+                    bst<T>(rF_out, off, c * cs, Fc);
+                    const double fd = (double)Fc;
+                    red[1] = fma(fd, fd, red[1]);
                     red[3] = fmax(red[3], fabs(fd));
                 } else {
                     bst<T>(rF_out, off, c * cs, Fc);
@@ -660,7 +697,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
 // One block of the force / FIRE step: tile `bid` of lattice L.  `nblocks`
 // is the lattice's own tile count; partials are indexed by tile, so the
 // reduction order does not depend on how blocks are dispatched.
-template <typename T, bool L23, bool STEP>
+template <typename T, bool L23, int MODE>
 __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, const T* __restrict__ qin,
                                            T* __restrict__ Fout, double* partials, FireDev* st,
                                            int nblocks, int bid) {
@@ -674,6 +711,7 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * L.zc;
     const int zc = min(L.zc, L.nz - z0);
 
+    constexpr bool STEP = MODE != MODE_FORCE;
     const T *q_in, *v_in = nullptr, *F_in = nullptr;
     T *q_out = nullptr, *v_out = nullptr, *F_out;
     T cv = T(1), cF = T(0), dt = T(0), hdt = T(0);
@@ -682,24 +720,25 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
         const int cur = st->cur;
         q_in = b.q[cur]; v_in = b.v[cur]; F_in = b.F[cur];
         q_out = b.q[1 - cur]; v_out = b.v[1 - cur]; F_out = b.F[1 - cur];
-        cv = T(st->c_v); cF = T(st->c_F);
         const double dtd = st->dt;
         dt = T(dtd); hdt = T(0.5 * dtd);
+        if (MODE == MODE_FIRE) { cv = T(st->c_v); cF = T(st->c_F); }
+        if (MODE == MODE_NAG) cv = T(st->mu);
     } else {
         q_in = qin;
         F_out = Fout;
     }
     double red[4] = {0.0, 0.0, 0.0, 0.0};
     if (L.tile_bulk[bid])
-        march<T, L23, STEP, true>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
+        march<T, L23, MODE, true>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
                                   sq, sm, red);
     else
-        march<T, L23, STEP, false>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
+        march<T, L23, MODE, false>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
                                    sq, sm, red);
     if (STEP) grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
 }
 
-template <typename T, bool L23, bool STEP>
+template <typename T, bool L23, int MODE>
 __global__ __launch_bounds__(NTHREADS) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
                                                     T* __restrict__ Fout, double* partials,
                                                     FireDev* st) {
@@ -707,7 +746,7 @@ __global__ __launch_bounds__(NTHREADS) void k_march(LatDev L, Bufs<T> b, const T
     int bid = (int)blockIdx.x;
     // keep neighbouring tiles on one XCD: dispatch is round-robin over 8 XCDs
     if ((nblocks & 7) == 0) bid = (bid & 7) * (nblocks >> 3) + (bid >> 3);
-    step_block<T, L23, STEP>(L, b, qin, Fout, partials, st, nblocks, bid);
+    step_block<T, L23, MODE>(L, b, qin, Fout, partials, st, nblocks, bid);
 }
 
 // ---------------------------------------------------------------------------
@@ -735,7 +774,7 @@ __global__ __launch_bounds__(NTHREADS) void k_march_batch(const MemberDev* __res
         b.q[i] = (T*)M.q[i]; b.v[i] = (T*)M.v[i]; b.F[i] = (T*)M.F[i];
     }
     const LatDev L = M.L;
-    step_block<T, L23, true>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
+    step_block<T, L23, MODE_FIRE>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
                              (int)blockIdx.x - off[m]);
 }
 
@@ -795,7 +834,7 @@ __global__ __launch_bounds__(256) void k_init_reduce(const T* __restrict__ F, co
     double r[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        double f = (double)F[i], w = (double)v[i];
+        double f = (double)F[i], w = v ? (double)v[i] : 0.0;
         r[0] = fma(f, w, r[0]);
         r[1] = fma(f, f, r[1]);
         r[2] = fma(w, w, r[2]);
@@ -816,20 +855,29 @@ __global__ void k_begin(FireDev* st, int64_t n_steps) {
 }
 
 // Brings the current state into buffer 0 and applies the pending steering.
+// Gradient descent leaves v untouched (with_v = false).
 template <typename T>
-__global__ __launch_bounds__(256) void k_finalize(Bufs<T> b, int64_t n, const FireDev* st) {
+__global__ __launch_bounds__(256) void k_finalize(Bufs<T> b, int64_t n, const FireDev* st, int with_v) {
     const int cur = st->cur;
     const T cv = T(st->c_v), cF = T(st->c_F);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        T v = b.v[cur][i], f = b.F[cur][i];
-        T vm = fma_t(cv, v, cF * f);
+        const T f = b.F[cur][i];
         if (cur) {
             b.q[0][i] = b.q[1][i];
             b.F[0][i] = f;
         }
-        b.v[0][i] = vm;
+        if (with_v) b.v[0][i] = fma_t(cv, b.v[cur][i], cF * f);
     }
+}
+
+// y = q + mu m: the Nesterov look-ahead point of a resumed state.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lookahead(const T* __restrict__ q, const T* __restrict__ m, T mu,
+                                                   T* __restrict__ y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = fma_t(mu, m[i], q[i]);
 }
 
 __global__ void k_reset_mix(FireDev* st) {
@@ -1008,30 +1056,38 @@ int launch_forces(const LatDev& L, bool l23, int prec, const void* q, void* F, v
     hipStream_t s = (hipStream_t)stream;
     if (prec == LQ_F64) {
         Bufs<double> b{};
-        if (l23) k_march<double, true, false><<<g, blk, 0, s>>>(L, b, (const double*)q, (double*)F, nullptr, nullptr);
-        else k_march<double, false, false><<<g, blk, 0, s>>>(L, b, (const double*)q, (double*)F, nullptr, nullptr);
+        if (l23) k_march<double, true, MODE_FORCE><<<g, blk, 0, s>>>(L, b, (const double*)q, (double*)F, nullptr, nullptr);
+        else k_march<double, false, MODE_FORCE><<<g, blk, 0, s>>>(L, b, (const double*)q, (double*)F, nullptr, nullptr);
     } else {
         Bufs<float> b{};
-        if (l23) k_march<float, true, false><<<g, blk, 0, s>>>(L, b, (const float*)q, (float*)F, nullptr, nullptr);
-        else k_march<float, false, false><<<g, blk, 0, s>>>(L, b, (const float*)q, (float*)F, nullptr, nullptr);
+        if (l23) k_march<float, true, MODE_FORCE><<<g, blk, 0, s>>>(L, b, (const float*)q, (float*)F, nullptr, nullptr);
+        else k_march<float, false, MODE_FORCE><<<g, blk, 0, s>>>(L, b, (const float*)q, (float*)F, nullptr, nullptr);
     }
     return hip_status(hipGetLastError());
 }
 
-int launch_fire_steps(const LatDev& L, bool l23, int prec, const void* bufs, double* partials,
+template <int MODE>
+static void launch_step(const LatDev& L, bool l23, int prec, const void* bufs, double* partials, FireDev* st,
+                        dim3 g, dim3 blk, hipStream_t s) {
+    if (prec == LQ_F64) {
+        const Bufs<double>& b = *(const Bufs<double>*)bufs;
+        if (l23) k_march<double, true, MODE><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
+        else k_march<double, false, MODE><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
+    } else {
+        const Bufs<float>& b = *(const Bufs<float>*)bufs;
+        if (l23) k_march<float, true, MODE><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
+        else k_march<float, false, MODE><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
+    }
+}
+
+int launch_fire_steps(const LatDev& L, bool l23, int prec, int method, const void* bufs, double* partials,
                       FireDev* st, int64_t n_steps, void* stream) {
     dim3 g((unsigned)n_step_blocks(L)), blk(NTHREADS);
     hipStream_t s = (hipStream_t)stream;
     for (int64_t i = 0; i < n_steps; ++i) {
-        if (prec == LQ_F64) {
-            const Bufs<double>& b = *(const Bufs<double>*)bufs;
-            if (l23) k_march<double, true, true><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
-            else k_march<double, false, true><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
-        } else {
-            const Bufs<float>& b = *(const Bufs<float>*)bufs;
-            if (l23) k_march<float, true, true><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
-            else k_march<float, false, true><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
-        }
+        if (method == LQ_METHOD_GD) launch_step<MODE_GD>(L, l23, prec, bufs, partials, st, g, blk, s);
+        else if (method == LQ_METHOD_NESTEROV) launch_step<MODE_NAG>(L, l23, prec, bufs, partials, st, g, blk, s);
+        else launch_step<MODE_FIRE>(L, l23, prec, bufs, partials, st, g, blk, s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return LQ_EHIP;
     }
@@ -1046,13 +1102,24 @@ int launch_begin(FireDev* st, int64_t n_steps, void* stream) {
     return hip_status(hipGetLastError());
 }
 
-int launch_finalize(const LatDev& L, int prec, const void* bufs, FireDev* st, void* stream) {
+int launch_finalize(const LatDev& L, int prec, bool with_v, const void* bufs, FireDev* st, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = 5 * L.N;
-    if (prec == LQ_F64) k_finalize<double><<<grid_1d(n), 256, 0, s>>>(*(const Bufs<double>*)bufs, n, st);
-    else k_finalize<float><<<grid_1d(n), 256, 0, s>>>(*(const Bufs<float>*)bufs, n, st);
+    if (prec == LQ_F64) k_finalize<double><<<grid_1d(n), 256, 0, s>>>(*(const Bufs<double>*)bufs, n, st, with_v);
+    else k_finalize<float><<<grid_1d(n), 256, 0, s>>>(*(const Bufs<float>*)bufs, n, st, with_v);
     if (hipGetLastError() != hipSuccess) return LQ_EHIP;
     k_reset_mix<<<1, 64, 0, s>>>(st);
+    return hip_status(hipGetLastError());
+}
+
+int launch_lookahead(const LatDev& L, int prec, const void* q, const void* m, double mu, void* y,
+                     void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = 5 * L.N;
+    if (prec == LQ_F64)
+        k_lookahead<double><<<grid_1d(n), 256, 0, s>>>((const double*)q, (const double*)m, mu, (double*)y, n);
+    else
+        k_lookahead<float><<<grid_1d(n), 256, 0, s>>>((const float*)q, (const float*)m, (float)mu, (float*)y, n);
     return hip_status(hipGetLastError());
 }
 

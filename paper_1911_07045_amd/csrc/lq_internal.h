@@ -76,8 +76,12 @@ struct FireDev {
     double dt_max, alpha0, f_inc, f_dec, f_alpha, tol;
     int64_t n_min, max_steps;
     uint32_t ticket;
-    uint32_t pad2;
+    int32_t method;   // LQ_METHOD_FIRE / LQ_METHOD_GD / LQ_METHOD_NESTEROV
+    double mu;        // Nesterov momentum
 };
+
+// march kernel variants
+enum : int { MODE_FORCE = 0, MODE_FIRE = 1, MODE_GD = 2, MODE_NAG = 3 };
 
 template <typename T>
 struct Bufs {
@@ -106,10 +110,12 @@ struct EnergyOut {
 int launch_forces(const LatDev& L, bool l23, int prec, const void* q, void* F, void* stream);
 int launch_fire_init_reduce(const LatDev& L, int prec, const void* F, const void* v,
                             double* partials, FireDev* st, void* stream);
-int launch_fire_steps(const LatDev& L, bool l23, int prec, const void* bufs, double* partials,
+int launch_fire_steps(const LatDev& L, bool l23, int prec, int method, const void* bufs, double* partials,
                       FireDev* st, int64_t n_steps, void* stream);
 int launch_begin(FireDev* st, int64_t n_steps, void* stream);
-int launch_finalize(const LatDev& L, int prec, const void* bufs, FireDev* st, void* stream);
+int launch_finalize(const LatDev& L, int prec, bool with_v, const void* bufs, FireDev* st, void* stream);
+int launch_lookahead(const LatDev& L, int prec, const void* q, const void* m, double mu, void* y,
+                     void* stream);
 int launch_fill_zero(void* p, int64_t bytes, void* stream);
 int launch_energy(const LatDev& L, bool l23, int prec, const void* q, double* partials,
                   EnergyOut* out, uint32_t* ticket, void* stream);

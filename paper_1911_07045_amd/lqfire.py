@@ -21,6 +21,7 @@ LAWS = {"nd": LQ_LAW_ND, "rp": LQ_LAW_RP, "fg": LQ_LAW_FG}
 ANCH_STRIDE = 21
 LQ_DIR_NORMAL, LQ_DIR_FIXED = 0, 1
 RUNNING, CONVERGED, MAX_STEPS, NONFINITE = 0, 1, 2, 3
+LQ_METHOD_FIRE, LQ_METHOD_GD, LQ_METHOD_NESTEROV = 0, 1, 2
 
 ERR_NAMES = {LQ_EINVAL: "LQ_EINVAL", LQ_EUNSUPPORTED: "LQ_EUNSUPPORTED", LQ_ENOMEM: "LQ_ENOMEM",
              LQ_EHIP: "LQ_EHIP", LQ_ENONFINITE: "LQ_ENONFINITE", LQ_ESTATE: "LQ_ESTATE"}
@@ -72,6 +73,11 @@ class FireReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class DescentParams(C.Structure):
+    _fields_ = [("method", C.c_int32), ("pad", C.c_int32), ("dt", C.c_double),
+                ("momentum", C.c_double), ("force_tol", C.c_double), ("max_steps", C.c_int64)]
+
+
 _lib = None
 
 
@@ -103,6 +109,10 @@ def lib():
             "lq_fire_step": (C.c_int, [vp, i64, C.POINTER(FireReport)]),
             "lq_minimize": (C.c_int, [vp, C.POINTER(FireParams), vp, vp, vp, vp, i64,
                                       C.POINTER(FireReport)]),
+            "lq_descent_init": (C.c_int, [vp, C.POINTER(DescentParams), vp, vp, vp, vp, i64,
+                                          C.POINTER(FireReport)]),
+            "lq_descent_minimize": (C.c_int, [vp, C.POINTER(DescentParams), vp, vp, vp, vp, i64,
+                                              C.POINTER(FireReport)]),
             "lq_last_error": (C.c_char_p, [vp]),
             "lq_batch_create": (C.c_int, [i32, vp, C.POINTER(vp)]),
             "lq_batch_destroy": (C.c_int, [vp]),
@@ -177,6 +187,12 @@ def make_records(records):
         v = r["nu"] if _is_fg(law, r["W"]) else r["n0"]
         arr[i].n0 = (C.c_double * 3)(*[float(x) for x in v])
     return arr, len(records)
+
+
+def make_descent_params(method, dt, momentum=0.0, force_tol=1e-9, max_steps=2000) -> DescentParams:
+    """method: "gd" or "nesterov" (or LQ_METHOD_*)."""
+    m = {"gd": LQ_METHOD_GD, "nesterov": LQ_METHOD_NESTEROV}.get(method, method)
+    return DescentParams(int(m), 0, float(dt), float(momentum), float(force_tol), int(max_steps))
 
 
 def make_fire_params(dt0=1e-3, dt_max=1e-2, alpha0=0.99, f_inc=1.1, f_dec=0.5, f_alpha=0.99, n_min=5,
@@ -336,6 +352,26 @@ class Lattice:
         self._bound = (q, v, F)
         return r, q, v, F
 
+    def descent_init(self, params, q, v, F, resume=None):
+        """Binds a gradient-descent or Nesterov run (lq_descent_init); advance it with fire_step."""
+        ws, off = self.workspace()
+        rep = None if resume is None else C.byref(resume)
+        _check(lib().lq_descent_init(self.h, C.byref(params), self._field(q, "q"), self._field(v, "v"),
+                                     self._field(F, "F"), C.c_void_p(ws.data_ptr() + off),
+                                     ws.numel() - off, rep), self.h)
+        self._bound = (q, v, F)
+
+    def descent_minimize(self, params, q, v=None, F=None):
+        v = self.zeros() if v is None else v
+        F = self.empty() if F is None else F
+        ws, off = self.workspace()
+        r = FireReport()
+        _check(lib().lq_descent_minimize(self.h, C.byref(params), self._field(q, "q"), self._field(v, "v"),
+                                         self._field(F, "F"), C.c_void_p(ws.data_ptr() + off),
+                                         ws.numel() - off, C.byref(r)), self.h)
+        self._bound = (q, v, F)
+        return r, q, v, F
+
 
 class Batch:
     """lq_batch: many bound lattices advanced by one launch per FIRE step."""
@@ -408,6 +444,10 @@ def fire_step(lat: Lattice, n_steps):
 
 def minimize(lat: Lattice, params, q, v=None, F=None):
     return lat.minimize(params, q, v, F)
+
+
+def descent_minimize(lat: Lattice, params, q, v=None, F=None):
+    return lat.descent_minimize(params, q, v, F)
 
 
 def lattice_from_config(cfg, prec=None, **kw) -> Lattice:

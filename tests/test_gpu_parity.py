@@ -247,6 +247,129 @@ def test_minimize_bulk_in_field_reaches_field_aligned_state():
     say(f"  steps {rep.step}, S {S:.6f} (S0 {lat.S0:.6f})")
 
 
+def _descent_trajectory(ora, p, lat, q0, method, dt, mu, steps, every, tol, prec="f64"):
+    prm_o = ora.descent_params(method, dt, mu, force_tol=0.0, max_steps=10 ** 6)
+    st, qo, mo, Fo = p.descent_init(prm_o, q0)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    q = to_dev(q0, dtype)
+    v, F = lat.empty(), lat.empty()
+    lat.descent_init(lqfire.make_descent_params(method, dt, mu, force_tol=0.0, max_steps=10 ** 6), q, v, F)
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        p.descent_steps(prm_o, st, qo, mo, Fo, k)
+        rep = lat.fire_step(k)
+        done += k
+        Fg = F.cpu().numpy().astype(np.float64)
+        err = np.abs(Fg - Fo).max() / np.abs(Fo).max()
+        assert err <= tol, f"step {done}: force error {err:.3e}"
+        assert np.abs(q.cpu().numpy() - qo).max() <= tol * max(1.0, np.abs(qo).max())
+        if method == "nesterov":
+            assert np.abs(v.cpu().numpy() - mo).max() <= tol * max(1e-3, np.abs(mo).max())
+            assert abs(rep.P - st.P) <= 1e-8 * abs(st.normF * st.normv) + 1e-300
+        assert rep.step == st.step and rep.status == st.status
+        assert rep.normF == pytest.approx(st.normF, rel=max(tol, 1e-9))
+    return rep, st
+
+
+@pytest.mark.parametrize("method,mu", [("gd", 0.0), ("nesterov", 0.9)])
+def test_descent_trajectory_walls_colloid_fg_field_L23(ora, method, mu):
+    """Gradient descent and Nesterov on a slab with a homeotropic colloid,
+    a degenerate planar wall and a field: q, m and F agree with the oracle
+    to 1e-10 over 120 steps."""
+    cfg = synth.colloid_slab(16, seed=15)
+    cfg["objects"][2]["radius"] = 3.5
+    cfg["objects"][1] = dict(kind="wall", axis=2, plane=15, law="rp", W=-2.0)
+    say(f"[descent] {method} colloid_slab16 L23 120 steps")
+    p, lat = pair(ora, cfg["shape"], L2=1.16, L3=0.7, objects=cfg["objects"], fields=[((0.0, 0.6, 0.8), 0.4)])
+    q0 = p.uniaxial(synth.random_directors(15, p.N))
+    _descent_trajectory(ora, p, lat, q0, method, 0.01, mu, 120, 30, 1e-10)
+
+
+def test_descent_fp32_and_ragged_open_box(ora):
+    """FP32 Nesterov on a ragged box with an open axis against the FP64
+    oracle: 1e-4 relative over 40 steps (FP32 rounding, compounded)."""
+    say("[descent] nesterov f32 ragged open")
+    p, lat = pair(ora, (37, 11, 9), (True, False, True), L2=0.9, L3=0.3, prec="f32")
+    q0 = p.uniaxial(synth.random_directors(16, p.N)).astype(np.float32).astype(np.float64)
+    _descent_trajectory(ora, p, lat, q0, "nesterov", 0.01, 0.8, 40, 10, 1e-4, prec="f32")
+
+
+def test_nesterov_resume_is_bitwise():
+    """Nesterov 25 + 15 steps equals 40 steps bit for bit, also when the
+    second part re-binds with lq_descent_init and the saved report (the
+    force is then rebuilt at the look-ahead point)."""
+    say("[descent] nesterov resume")
+    cfg = synth.colloid_slab(16, seed=17)
+    cfg["objects"][2]["radius"] = 3.0
+    prm = lqfire.make_descent_params("nesterov", 0.01, 0.85, force_tol=0.0, max_steps=10 ** 6)
+    runs = []
+    for split in ([40], [25, 15], "resume"):
+        lat = lqfire.lattice_from_config(cfg)
+        q = lat.set_uniaxial(to_dev(synth.random_directors(17, lat.N), torch.float64), lat.empty())
+        v, F = lat.empty(), lat.empty()
+        lat.descent_init(prm, q, v, F)
+        if split == "resume":
+            rep = lat.fire_step(25)
+            q2, v2, F2 = q.clone(), v.clone(), lat.empty()
+            lat2 = lqfire.lattice_from_config(cfg)
+            lat2.descent_init(prm, q2, v2, F2, resume=rep)
+            assert torch.equal(F2, F)
+            lat2.fire_step(15)
+            q, v, F = q2, v2, F2
+        else:
+            for n in split:
+                lat.fire_step(n)
+        runs.append((q.cpu(), v.cpu(), F.cpu()))
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            assert torch.equal(a, b)
+
+
+def test_descent_minimize_reaches_exact_wall_minimum():
+    """GD and Nesterov relax the oriented-wall box to Q0 everywhere,
+    E = N_sim f0; GD leaves v untouched."""
+    objs = [dict(kind="wall", axis=2, plane=0, law="nd", W=0.5, dir=(1.0, 0.0, 0.0)),
+            dict(kind="wall", axis=2, plane=9, law="nd", W=0.5, dir=(1.0, 0.0, 0.0))]
+    steps = {}
+    for method, mu in (("gd", 0.0), ("nesterov", 0.9)):
+        say(f"[descent] minimize walls {method}")
+        lat = lqfire.Lattice((12, 10, 10), L2=1.16, L3=1.16)
+        lat.set_boundaries(objs)
+        q = lat.set_uniaxial(to_dev(synth.random_directors(18, lat.N), torch.float64), lat.empty())
+        v = torch.full_like(q, 7.0)
+        rep, q, v, F = lat.descent_minimize(
+            lqfire.make_descent_params(method, 0.01, mu, force_tol=1e-9, max_steps=200000), q,
+            v if method == "gd" else None)
+        assert rep.status == lqfire.CONVERGED, rep.as_dict()
+        if method == "gd":
+            assert bool((v == 7.0).all())
+        s0 = lat.S0
+        f0 = 0.75 * A * s0 ** 2 + 0.25 * B * s0 ** 3 + 9.0 / 16.0 * C * s0 ** 4
+        e = lat.energy(q)
+        assert abs(e["total"] - e["n_sim"] * f0) <= 1e-9 * abs(e["n_sim"] * f0)
+        steps[method] = rep.step
+    say(f"  steps {steps}")
+    assert steps["nesterov"] < steps["gd"]
+
+
+def test_descent_divergence_is_reported_not_finite():
+    """A GD step above the stability limit blows up: the run stops with
+    LQ_ENONFINITE and status NONFINITE instead of running on."""
+    say("[descent] divergence")
+    lat = lqfire.Lattice((12, 10, 10), L2=1.16, L3=1.16)
+    q = lat.set_uniaxial(to_dev(synth.random_directors(18, lat.N), torch.float64), lat.empty())
+    v, F = lat.empty(), lat.empty()
+    lat.descent_init(lqfire.make_descent_params("gd", 0.05, force_tol=0.0, max_steps=10 ** 6), q, v, F)
+    with pytest.raises(lqfire.LQError) as e:
+        lat.fire_step(2000)
+    assert e.value.code == lqfire.LQ_ENONFINITE
+    import ctypes as Cc
+    r = lqfire.FireReport()
+    assert lqfire.lib().lq_fire_step(lat.h, 5, Cc.byref(r)) == lqfire.LQ_ENONFINITE
+    assert r.status == lqfire.NONFINITE and r.step < 2000
+
+
 def test_fire_steps_resume_bitwise():
     """fire_step(30) + fire_step(20) equals fire_step(50) bit for bit, and so
     does re-binding with the saved controller (lq_fire_init with resume)."""
@@ -374,6 +497,18 @@ def test_error_paths():
     assert rep.status == lqfire.MAX_STEPS and rep.step == 0
     with pytest.raises(ValueError):
         lat.compute_forces(q.cpu())
+    # descent parameters
+    for bad in (lqfire.make_descent_params("gd", 0.0), lqfire.make_descent_params("nesterov", 0.1, 1.0),
+                lqfire.make_descent_params(7, 0.1), lqfire.make_descent_params("gd", float("nan"))):
+        with pytest.raises(lqfire.LQError) as e:
+            lat.descent_init(bad, q, v, F)
+        assert e.value.code == lqfire.LQ_EINVAL
+    # a descent-bound lattice cannot join a FIRE batch
+    lat.descent_init(lqfire.make_descent_params("gd", 0.01), q, v, F)
+    bt = lqfire.Batch(2)
+    with pytest.raises(lqfire.LQError) as e:
+        bt.add(lat)
+    assert e.value.code == lqfire.LQ_EINVAL
     # fields: non-finite values are refused; a new field unbinds FIRE
     with pytest.raises(lqfire.LQError) as e:
         lat.set_field([((1.0, float("inf"), 0.0), 1.0)])
