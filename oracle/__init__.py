@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
 class _Problem(C.Structure):
     _fields_ = [("n", C.c_int64 * 3), ("periodic", C.c_int32 * 3),
                 ("A", C.c_double), ("B", C.c_double), ("C", C.c_double),
-                ("L1", C.c_double), ("L2", C.c_double), ("L3", C.c_double),
+                ("L1", C.c_double), ("L2", C.c_double), ("L3", C.c_double), ("L4", C.c_double),
                 ("type", C.c_void_p), ("n_pairs", C.c_int64), ("pair_site", C.c_void_p),
                 ("pair_W", C.c_void_p), ("pair_Q0", C.c_void_p), ("pair_kind", C.c_void_p),
                 ("pair_nu", C.c_void_p), ("S0", C.c_double), ("hfield", C.c_double * 9)]
@@ -151,7 +151,7 @@ class Problem:
 
     def __init__(self, shape, periodic=(True, True, True), A=-0.172, B=-2.12, C_=1.73,
                  L1=2.32, L2=0.0, L3=0.0, objects=(), site_records=(), object_sites=(),
-                 types=None, pairs=None, fields=()):
+                 types=None, pairs=None, fields=(), L4=0.0):
         """fields: (h, chi) pairs giving f_ext = -(1/3) sum chi (h.Q.h), sec. II.A.3
         (chi = mu0 dchi or eps0 deps in units of |A|, h the field vector)."""
         self.shape = tuple(int(s) for s in shape)
@@ -159,7 +159,7 @@ class Problem:
         for k in range(3):
             if self.periodic[k] and self.shape[k] < 3:
                 raise ValueError("a periodic axis needs at least 3 sites")
-        self.A, self.B, self.C, self.L1, self.L2, self.L3 = A, B, C_, L1, L2, L3
+        self.A, self.B, self.C, self.L1, self.L2, self.L3, self.L4 = A, B, C_, L1, L2, L3, L4
         self.S0 = S0(A, B, C_)
         if types is None:
             types, ps, pw, pq, pk, pn = rasterize(self.shape, self.periodic, list(objects), self.S0,
@@ -182,7 +182,7 @@ class Problem:
         self.N = nx * ny * nz
         self._s = _Problem((C.c_int64 * 3)(nx, ny, nz),
                            (C.c_int32 * 3)(*[int(p) for p in self.periodic]),
-                           A, B, C_, L1, L2, L3, self.types.ctypes.data, len(self.pair_site),
+                           A, B, C_, L1, L2, L3, L4, self.types.ctypes.data, len(self.pair_site),
                            self.pair_site.ctypes.data, self.pair_W.ctypes.data,
                            self.pair_Q0.ctypes.data, self.pair_kind.ctypes.data,
                            self.pair_nu.ctypes.data, self.S0,

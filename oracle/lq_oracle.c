@@ -13,7 +13,7 @@
  * minimization", and section II):
  *   - q = (Qxx, Qxy, Qxz, Qyy, Qyz) per site, Qzz = -Qxx - Qyy (sec. III.B);
  *   - bulk density, Eq. (fphase);
- *   - distortion density, Eq. (fdistortionFull) with L4 = L6 = 0, built from
+ *   - distortion density, Eq. (fdistortionFull) with L6 = 0, built from
  *     the one-sided differences of Eq. (onesidedderivatives) and averaged over
  *     every allowed forward/backward choice per axis (sec. III.B, text after
  *     Eq. onesidedderivatives);
@@ -39,6 +39,7 @@ typedef struct {
     int32_t periodic[3];   /* 1 = periodic axis */
     double A, B, C;        /* bulk coefficients, Eq. (fphase) */
     double L1, L2, L3;     /* distortion coefficients, Eq. (fdistortionFull) */
+    double L4;             /* chiral term of Eq. (fdistortionFull) */
     const uint8_t *type;   /* per site: 0 bulk, 1 boundary, 2 object */
     int64_t n_pairs;       /* anchoring (site, surface) pairs */
     const int64_t *pair_site;
@@ -125,8 +126,15 @@ static void grad_bulk(const ora_problem *p, const double Q[3][3], double G[3][3]
         }
 }
 
-/* Eq. (fdistortionFull) with L4 = L6 = 0; d[k][i][j] stands for dQ_ij/dx_k */
-static double f_dist(const ora_problem *p, double d[3][3][3])
+/* Levi-Civita symbol */
+static double eps3(int a, int b, int c)
+{
+    return (double)((a - b) * (b - c) * (c - a)) / 2.0;
+}
+
+/* Eq. (fdistortionFull) with L6 = 0; d[k][i][j] stands for dQ_ij/dx_k and
+ * Q is the tensor at the site (it enters the chiral L4 term) */
+static double f_dist(const ora_problem *p, const double Q[3][3], double d[3][3][3])
 {
     double e1 = 0.0, e2 = 0.0, e3 = 0.0;
     for (int k = 0; k < 3; ++k)
@@ -140,21 +148,44 @@ static double f_dist(const ora_problem *p, double d[3][3][3])
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             for (int k = 0; k < 3; ++k) e3 += d[j][i][k] * d[k][i][j];
-    return 0.5 * p->L1 * e1 + 0.5 * p->L2 * e2 + 0.5 * p->L3 * e3;
+    double e4 = 0.0;
+    for (int l = 0; l < 3; ++l)
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) {
+                double e = eps3(l, i, k);
+                if (e == 0.0) continue;
+                for (int j = 0; j < 3; ++j) e4 += e * Q[l][j] * d[k][i][j];
+            }
+    return 0.5 * p->L1 * e1 + 0.5 * p->L2 * e2 + 0.5 * p->L3 * e3 + 0.5 * p->L4 * e4;
 }
 
 /* derivative of f_dist with respect to d[k][i][j]:
- *   L1 d_k,ij + L2 delta_kj sum_m d_m,im + L3 d_j,ik                       */
-static void grad_dist(const ora_problem *p, double d[3][3][3], double g[3][3][3])
+ *   L1 d_k,ij + L2 delta_kj sum_m d_m,im + L3 d_j,ik
+ *   + L4/2 sum_l eps_lik Q_lj                                             */
+static void grad_dist(const ora_problem *p, const double Q[3][3], double d[3][3][3], double g[3][3][3])
 {
     for (int k = 0; k < 3; ++k)
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) {
-                double div = 0.0;
+                double div = 0.0, chi = 0.0;
                 for (int m = 0; m < 3; ++m) div += d[m][i][m];
+                for (int l = 0; l < 3; ++l) chi += eps3(l, i, k) * Q[l][j];
                 g[k][i][j] = p->L1 * d[k][i][j] + (k == j ? p->L2 * div : 0.0)
-                             + p->L3 * d[j][i][k];
+                             + p->L3 * d[j][i][k] + 0.5 * p->L4 * chi;
             }
+}
+
+/* derivative of f_dist with respect to the site tensor Q_lj (only the L4
+ * term depends on it): L4/2 sum_ik eps_lik d_k,ij */
+static void grad_dist_site(const ora_problem *p, double d[3][3][3], double h[3][3])
+{
+    for (int l = 0; l < 3; ++l)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int k = 0; k < 3; ++k) s += eps3(l, i, k) * d[k][i][j];
+            h[l][j] = 0.5 * p->L4 * s;
+        }
 }
 
 /* ---- lattice helpers ---- */
@@ -243,33 +274,42 @@ static double e_dist_site(const ora_problem *p, const double *q, int64_t x)
     options_at(p, x, &o);
     int ncomb = o.n_opt[0] * o.n_opt[1] * o.n_opt[2];
     double sum = 0.0;
-    double d[3][3][3];
+    double d[3][3][3], Qx[3][3];
+    load_Q(p, q, x, Qx);
     for (int a = 0; a < o.n_opt[0]; ++a)
         for (int b = 0; b < o.n_opt[1]; ++b)
             for (int c = 0; c < o.n_opt[2]; ++c) {
                 int s[3] = {o.opt[0][a], o.opt[1][b], o.opt[2][c]};
                 for (int k = 0; k < 3; ++k) difference(p, q, x, &o, k, s[k], d[k]);
-                sum += f_dist(p, d);
+                sum += f_dist(p, Qx, d);
             }
     return sum / (double)ncomb;
 }
 
 /* Adds d(averaged distortion energy of site x)/dQ(y) to G, by the chain rule
  * through every combination of site x: the difference along axis k depends
- * on Q(y) with coefficient +1 or -1 when y is one of its two end points. */
+ * on Q(y) with coefficient +1 or -1 when y is one of its two end points, and
+ * for y = x the chiral term also depends on Q(x) itself. */
 static void add_dist_grad_from(const ora_problem *p, const double *q, int64_t x,
                                int64_t y, double G[3][3])
 {
     site_options o;
     options_at(p, x, &o);
     int ncomb = o.n_opt[0] * o.n_opt[1] * o.n_opt[2];
-    double d[3][3][3], g[3][3][3];
+    double d[3][3][3], g[3][3][3], Qx[3][3];
+    load_Q(p, q, x, Qx);
     for (int a = 0; a < o.n_opt[0]; ++a)
         for (int b = 0; b < o.n_opt[1]; ++b)
             for (int c = 0; c < o.n_opt[2]; ++c) {
                 int s[3] = {o.opt[0][a], o.opt[1][b], o.opt[2][c]};
                 for (int k = 0; k < 3; ++k) difference(p, q, x, &o, k, s[k], d[k]);
-                grad_dist(p, d, g);
+                grad_dist(p, Qx, d, g);
+                if (x == y && p->L4 != 0.0) {
+                    double h[3][3];
+                    grad_dist_site(p, d, h);
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j) G[i][j] += h[i][j] / (double)ncomb;
+                }
                 for (int k = 0; k < 3; ++k) {
                     double coef = 0.0;
                     if (s[k] > 0) {

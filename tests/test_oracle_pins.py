@@ -726,3 +726,79 @@ def test_descent_stop_tests(ora):
     assert st.status == ora.MAX_STEPS and st.step == 17 and len(xs) == 18
     st, xs, tr, m, F = ora.descent_generic(ora.descent_params("gd", 0.5, force_tol=10.0), [1.0, 1.0], f, 5)
     assert st.status == ora.CONVERGED and st.step == 0 and len(xs) == 1
+
+
+# ---- the chiral L4 term of Eq. (fdistortionFull) ----
+
+def _levi_civita():
+    e = np.zeros((3, 3, 3))
+    for (a, b, c), sgn in {(0, 1, 2): 1, (1, 2, 0): 1, (2, 0, 1): 1,
+                           (0, 2, 1): -1, (2, 1, 0): -1, (1, 0, 2): -1}.items():
+        e[a, b, c] = sgn
+    return e
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_L4_helix_matches_frank_oseen_twist_through_the_mapping(ora, m):
+    """With L4 = -8 q0 K2 / (9 S^2) (the paper's L<->K identification), the
+    L4 term of a uniaxial helix n = (cos kz, sin kz, 0) equals the Frank-Oseen
+    cross term K2 q0 n.(curl n) = -K2 q0 k.  On the periodic lattice the
+    averaged one-sided z-differences are central differences, which scale
+    the exact derivative of cos 2kz, sin 2kz by sin(2k)/(2k), so the lattice
+    energy per site is exactly -K2 q0 sin(2k)/2."""
+    nz = 16
+    k = 2 * np.pi * m / nz
+    K2, q0 = 1.7, 0.35
+    S = 0.53
+    L4 = -8.0 * q0 * K2 / (9.0 * S * S)
+    p = ora.Problem((3, 4, nz), L1=0.0, L4=L4)
+    z = np.arange(nz, dtype=np.float64)
+    n = np.zeros((3, nz, 4, 3))
+    n[0] = np.cos(k * z)[:, None, None]
+    n[1] = np.sin(k * z)[:, None, None]
+    q = p.uniaxial(n.reshape(3, -1), S)
+    _, t = p.energy(q, terms=True)
+    ref = -K2 * q0 * np.sin(2 * k) / 2.0
+    assert abs(t[1] / p.N - ref) <= 1e-14 * abs(ref)
+    # the opposite handedness costs the opposite
+    n[1] *= -1.0
+    _, t = p.energy(p.uniaxial(n.reshape(3, -1), S), terms=True)
+    assert abs(t[1] / p.N + ref) <= 1e-14 * abs(ref)
+
+
+def test_L4_linear_field_is_exact_on_an_open_box(ora):
+    """For a Q field linear in position every allowed one-sided difference is
+    the exact derivative, so with only L4 on, the averaged lattice energy is
+    sum over sites of L4/2 eps_lik Q_lj(x) dQ_ij/dx_k, also at the faces of
+    an open box."""
+    rng = np.random.default_rng(61)
+    shape = (4, 3, 5)
+    p = ora.Problem(shape, (False, False, False), L1=0.0, L4=0.8)
+
+    def sym_traceless():
+        M = rng.standard_normal((3, 3))
+        M = M + M.T
+        return M - np.trace(M) / 3.0 * np.eye(3)
+
+    Q0 = sym_traceless()
+    G = [sym_traceless() for _ in range(3)]
+    nx, ny, nz = shape
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    Q = Q0[None, None, None] + X[..., None, None] * G[0] + Y[..., None, None] * G[1] + Z[..., None, None] * G[2]
+    q = np.stack([Q[..., 0, 0], Q[..., 0, 1], Q[..., 0, 2], Q[..., 1, 1], Q[..., 1, 2]])
+    _, t = p.energy(q, terms=True)
+    eps = _levi_civita()
+    dQ = np.stack(G)  # [k, i, j]
+    ref = 0.5 * 0.8 * np.einsum("lik,zyxlj,kij->", eps, Q, dQ)
+    assert abs(t[1] - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("periodic", [(True, True, True), (False, True, False)])
+def test_forces_exact_gradient_with_L4(ora, periodic):
+    p = ora.Problem((4, 3, 5), periodic, L1=2.32, L2=0.9, L3=0.4, L4=-0.7, objects=[
+        dict(kind="sphere", center=(1.5, 1.0, 2.0), radius=0.9, law="nd", W=0.6, dir="normal")],
+        fields=[((0.1, 0.2, 0.3), 0.5)])
+    q = rand_q(p, seed=62)
+    F = p.forces(q)
+    Ffd = five_point_forces(p, q)
+    assert np.abs(F - Ffd).max() <= 1e-10 * np.abs(F).max()
