@@ -37,7 +37,7 @@ extern "C" {
 /* ---- return codes ---- */
 #define LQ_OK 0
 #define LQ_EINVAL (-1)        /* bad argument: sizes, pointers, NaN/negative parameters */
-#define LQ_EUNSUPPORTED (-2)  /* valid in the paper but not built: L4, L6 */
+#define LQ_EUNSUPPORTED (-2)  /* valid in the paper but not built: L6 */
 #define LQ_ENOMEM (-3)        /* workspace too small, or a device allocation failed */
 #define LQ_EHIP (-4)          /* a HIP runtime call failed */
 #define LQ_ENONFINITE (-5)    /* a FIRE reduction produced NaN or Inf */
@@ -59,7 +59,8 @@ typedef struct {
     int32_t prec;        /* LQ_F64 or LQ_F32 */
     double A, B, C;      /* bulk coefficients, Eq. (fphase); C > 0 */
     double L1, L2, L3;   /* distortion coefficients, Eq. (fdistortionFull) */
-    double L4, L6;       /* must be 0 (LQ_EUNSUPPORTED otherwise) */
+    double L4;           /* chiral term (L4/2) eps_lik Q_lj dQ_ij/dx_k of Eq. (fdistortionFull) */
+    double L6;           /* must be 0 (LQ_EUNSUPPORTED otherwise) */
 } lq_params;
 
 /* Creates a lattice with every site bulk.  stream: a hipStream_t, or NULL for

@@ -107,8 +107,8 @@ static int check_params(const lq_params* p, std::string& err) {
             err = "non-finite constant";
             return LQ_EINVAL;
         }
-    if (p->L4 != 0.0 || p->L6 != 0.0) {
-        err = "L4 and L6 terms are not built";
+    if (p->L6 != 0.0) {
+        err = "the L6 term is not built";
         return LQ_EUNSUPPORTED;
     }
     return LQ_OK;
@@ -197,7 +197,7 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     d.nx = (int)p.n[0]; d.ny = (int)p.n[1]; d.nz = (int)p.n[2];
     for (int k = 0; k < 3; ++k) d.per[k] = p.periodic[k];
     d.N = lat->N;
-    d.A = p.A; d.B = p.B; d.C = p.C; d.L1 = p.L1; d.L2 = p.L2; d.L3 = p.L3;
+    d.A = p.A; d.B = p.B; d.C = p.C; d.L1 = p.L1; d.L2 = p.L2; d.L3 = p.L3; d.L4 = p.L4;
     d.zc = pick_zc(p);
     d.ntx = (int)((p.n[0] + TX - 1) / TX);
     d.nty = (int)((p.n[1] + TY - 1) / TY);
@@ -241,7 +241,7 @@ int lq_lattice_create(const lq_params* p, void* stream, lq_lattice** out) {
     lat->p = *p;
     lat->S0 = bulk_S0(*p);
     lat->stream = (hipStream_t)stream;
-    lat->l23 = p->L2 != 0.0 || p->L3 != 0.0;
+    lat->l23 = p->L2 != 0.0 || p->L3 != 0.0 || p->L4 != 0.0;
     lat->N = p->n[0] * p->n[1] * p->n[2];
     hipError_t e = hipGetDevice(&lat->device);
     if (e != hipSuccess) {

@@ -2,7 +2,7 @@
 // the fused force + FIRE step, the FIRE controller, the energy and helpers.
 //
 // The energy is the paper's discretization (sec. III.B): bulk Eq. (fphase),
-// distortion Eq. (fdistortionFull) (L4 = L6 = 0) from one-sided differences
+// distortion Eq. (fdistortionFull) (L6 = 0) from one-sided differences
 // Eq. (onesidedderivatives) averaged over every allowed forward/backward
 // choice per axis, plus anchoring (sec. II.A.4) and external fields
 // (sec. II.A.3).  Because the choices on different axes are independent, the
@@ -193,6 +193,53 @@ __device__ __forceinline__ void cross_h(int j, const T Ck[3][5], T L2, T L3, T h
     pT(H, h);
 }
 
+// Levi-Civita symbol
+__host__ __device__ constexpr int eps3(int a, int b, int c) { return ((a - b) * (b - c) * (c - a)) / 2; }
+
+// Chiral term (L4) of Eq. (fdistortionFull), E4(x) = L4/2 eps_lik Q_lj(x) C_k,ij(x).
+// Its derivative with respect to the site tensor: P^T of sum_ik eps_aik C_k,ib.
+template <typename T>
+__device__ __forceinline__ void chiral_site(const T C[3][5], T h[5]) {
+    T H[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) H[a][b] = T(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        T Ck[3][3];
+        full_of(C[k], Ck);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                if (eps3(a, i, k) == 0) continue;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) H[a][b] += T(eps3(a, i, k)) * Ck[i][b];
+            }
+    }
+    pT(H, h);
+}
+
+// Derivative of E4(x) with respect to the tensor of a site that enters C_k(x)
+// with coefficient 1: P^T of sum_l eps_lak Q_lb(x).
+template <typename T>
+__device__ __forceinline__ void chiral_nb(int k, const T qx[5], T h[5]) {
+    T Qx[3][3], H[3][3];
+    full_of(qx, Qx);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            T v = T(0);
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+                if (eps3(l, a, k) != 0) v += T(eps3(l, a, k)) * Qx[l][b];
+            H[a][b] = v;
+        }
+    pT(H, h);
+}
+
 // ---------------------------------------------------------------------------
 // Stencil view used by the force: offsets (dx, dy, dz) in {-1, 0, 1} around
 // the centre, read from the LDS slots of the planes below, at and above the
@@ -327,6 +374,39 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK>& P, uint3
                 cross_h(j, Ck, L2, L3, h);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) g[c] = fma_t(a0, h[c], g[c]);
+            }
+        }
+        if (L.L4 != 0.0) {
+            // chiral term: the site's own tensor, then every C_k(x) holding Q(centre)
+            const T hL4 = T(0.5 * L.L4);
+            T Cc[3][5], h[5];
+            mean_diffs(P, 0, 0, 0, -1, m0, Cc);
+            chiral_site(Cc, h);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) g[c] = fma_t(hL4, h[c], g[c]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+#pragma unroll
+                for (int s = -1; s <= 1; s += 2) {
+                    int dx, dy, dz;
+                    unit(k, -s, dx, dy, dz);
+                    T ap, a0, am;
+                    mean_diff_coef(P.mask(dx, dy, dz), k, ap, a0, am);
+                    const T coef = s > 0 ? ap : am;
+                    if (coef == T(0)) continue;
+                    T qx[5];
+                    P.load5(dx, dy, dz, qx);
+                    chiral_nb(k, qx, h);
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) g[c] = fma_t(hL4 * coef, h[c], g[c]);
+                }
+                T ap, a0, am;
+                mean_diff_coef(m0, k, ap, a0, am);
+                if (a0 != T(0)) {
+                    chiral_nb(k, q0, h);
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) g[c] = fma_t(hL4 * a0, h[c], g[c]);
+                }
             }
         }
     }
@@ -989,6 +1069,15 @@ __global__ __launch_bounds__(256) void k_energy(LatDev L, const T* __restrict__ 
                 for (int k = j + 1; k < 3; ++k)
                     for (int i = 0; i < 3; ++i)
                         ed += L.L2 * Cf[j][i][j] * Cf[k][i][k] + L.L3 * Cf[j][i][k] * Cf[k][i][j];
+            // chiral term L4/2 eps_lik Q_lj C_k,ij
+            double e4 = 0.0;
+            for (int l = 0; l < 3; ++l)
+                for (int i = 0; i < 3; ++i)
+                    for (int k = 0; k < 3; ++k) {
+                        if (eps3(l, i, k) == 0) continue;
+                        for (int j = 0; j < 3; ++j) e4 += eps3(l, i, k) * Q[l][j] * Cf[k][i][j];
+                    }
+            ed += 0.5 * L.L4 * e4;
         }
         e_d += ed;
         double qe = 0.0;

@@ -59,7 +59,7 @@ struct LatDev {
     const int32_t* anch_index;  // per site: 1 + row of anch_data, 0 when not anchored
     const double* anch_data;    // ANCH_STRIDE per anchored site
     double ext[5];              // constant external-field force per simulated site
-    double A, B, C, L1, L2, L3;
+    double A, B, C, L1, L2, L3, L4;
     int zc, ntx, nty, ntz;
 };
 

@@ -147,9 +147,9 @@ def test_error_codes_on_the_host():
     # no real S0 while anchoring is requested
     assert _rc(lambda: lqfire.rasterize(box, (True, True, True), [dict(kind="wall", axis=0, plane=0, W=1.0)],
                                         C_=-1.0)) == lqfire.LQ_EINVAL
-    # L4 / L6 are not built; lq_lattice_create rejects them before touching a device
+    # L6 is not built; lq_lattice_create rejects it before touching a device
     import ctypes as Cc
-    p = lqfire.make_params(box, L4=0.1)
+    p = lqfire.make_params(box, L6=0.1)
     h = Cc.c_void_p()
     assert lqfire.lib().lq_lattice_create(Cc.byref(p), None, Cc.byref(h)) == lqfire.LQ_EUNSUPPORTED
     p = lqfire.make_params((8, 8, 8), prec=lqfire.LQ_F32)

@@ -29,10 +29,10 @@ def _gpu():
 
 
 def pair(ora, shape, periodic=(True, True, True), L2=0.0, L3=0.0, objects=(), records=(), osites=(),
-         prec="f64", L1=2.32, fields=()):
+         prec="f64", L1=2.32, fields=(), L4=0.0):
     p = ora.Problem(shape, periodic, L1=L1, L2=L2, L3=L3, objects=objects, site_records=records,
-                    object_sites=osites, fields=fields)
-    lat = lqfire.Lattice(shape, periodic, prec, L1=L1, L2=L2, L3=L3)
+                    object_sites=osites, fields=fields, L4=L4)
+    lat = lqfire.Lattice(shape, periodic, prec, L1=L1, L2=L2, L3=L3, L4=L4)
     if objects or records or len(osites):
         lat.set_boundaries(objects, records, osites)
     if fields:
@@ -79,6 +79,12 @@ CASES = {
                  dict(site=1500, law="rp", W=-3.0, nu=(0.0, 0.6, 0.8))], osites=[1700]),
     "field_only_open_L23": dict(shape=(37, 6, 5), periodic=(False, True, False), L2=0.9, L3=1.3,
                                 fields=[((0.0, 0.8, 0.6), 1.5)]),
+    "chiral_L4_only_ragged": dict(shape=(35, 10, 7), L2=0.0, L3=0.0, L4=-0.9),
+    "chiral_L234_walls_colloid_open": dict(shape=(30, 19, 12), periodic=(True, False, True), L2=1.16, L3=0.7,
+                                           L4=0.6, objects=[
+        dict(kind="wall", axis=2, plane=0, law="nd", W=0.5, dir=(1.0, 0.0, 0.0)),
+        dict(kind="wall", axis=2, plane=11, law="fg", W=0.7),
+        dict(kind="sphere", center=(14.2, 9.1, 5.5), radius=3.3, law="rp", W=5.0, dir="normal")]),
     "sandwiched_plane_L23": dict(shape=(66, 5, 3), L2=1.16, L3=0.3, objects=[
         dict(kind="wall", axis=2, plane=0, law="nd", W=0.7, dir=(0.0, 1.0, 0.0)),
         dict(kind="wall", axis=2, plane=2, law="nd", W=0.2, dir="normal")]),
@@ -107,7 +113,8 @@ def test_forces_and_energy_fp64(ora, name):
 
 
 @pytest.mark.parametrize("name", ["bulk32_L1", "ragged_periodic_L23", "colloid_slab24_L23",
-                                  "patterned_records_L23", "fg_walls_sphere_field_L23"])
+                                  "patterned_records_L23", "fg_walls_sphere_field_L23",
+                                  "chiral_L234_walls_colloid_open"])
 def test_forces_and_energy_fp32(ora, name):
     c = dict(CASES[name])
     say(f"[forces f32] {name} {c['shape']}")
@@ -189,6 +196,16 @@ def test_fire_trajectory_fg_sphere_field_L23(ora):
     p, lat = pair(ora, c["shape"], c["periodic"], L2=c["L2"], L3=c["L3"], objects=c["objects"],
                   fields=c["fields"])
     q0 = p.uniaxial(synth.random_directors(9, p.N))
+    _fire_trajectory(ora, p, lat, q0, 150, 10, 1e-10)
+
+
+def test_fire_trajectory_chiral_L4(ora):
+    """The chiral L4 term with L2/L3, walls and a colloid on a box open in y:
+    forces agree to 1e-10 over 150 FIRE steps."""
+    c = CASES["chiral_L234_walls_colloid_open"]
+    say("[fire] chiral L4 150 steps")
+    p, lat = pair(ora, c["shape"], c["periodic"], L2=c["L2"], L3=c["L3"], L4=c["L4"], objects=c["objects"])
+    q0 = p.uniaxial(synth.random_directors(19, p.N))
     _fire_trajectory(ora, p, lat, q0, 150, 10, 1e-10)
 
 
