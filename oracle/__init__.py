@@ -4,8 +4,9 @@ TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check in __graft_entry__.py
 and the cpu_baseline leg of bench.py may import this package.  The GPU library
 never imports it and shares no code with it.
 
-The arithmetic lives in lq_oracle.c (energy, its explicit gradient, FIRE) and
-geometry.py (site types and anchoring pairs); this module loads the C part
+The arithmetic lives in lq_oracle.c (energy, its explicit gradient, FIRE,
+gradient descent, Nesterov), geometry.py (site types and anchoring pairs) and
+director.py (director and defect extraction); this module loads the C part
 with ctypes and wraps it.  Every function cites the passage of the paper it
 follows in its source.
 """
@@ -17,6 +18,7 @@ import subprocess
 
 import numpy as np
 
+from .director import directors  # noqa: F401
 from .geometry import q_from_director, rasterize  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

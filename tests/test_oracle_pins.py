@@ -802,3 +802,54 @@ def test_forces_exact_gradient_with_L4(ora, periodic):
     F = p.forces(q)
     Ffd = five_point_forces(p, q)
     assert np.abs(F - Ffd).max() <= 1e-10 * np.abs(F).max()
+
+
+# ---- director and defect extraction (Eq. Qtensor; the GUI's display) ----
+
+def _rotation(rng):
+    A = rng.standard_normal((3, 3))
+    R, _ = np.linalg.qr(A)
+    return R * np.sign(np.linalg.det(R))
+
+
+def test_director_of_biaxial_tensors_from_eq_qtensor(ora):
+    """For Q = 3/2 S (nn - I/3) + 1/2 S_B (mm - ll) with 3 S > |S_B| the
+    largest eigenvalue is S along n (the other two are (-S +- S_B)/2), so the
+    extracted director is +-n and lambda_max = S."""
+    rng = np.random.default_rng(71)
+    N = 200
+    ns, Qs, Ss = [], [], []
+    for _ in range(N):
+        R = _rotation(rng)
+        n, m, l = R[:, 0], R[:, 1], R[:, 2]
+        S = rng.uniform(0.05, 0.9)
+        SB = rng.uniform(-0.9, 0.9) * S
+        Q = 1.5 * S * (np.outer(n, n) - np.eye(3) / 3) + 0.5 * SB * (np.outer(m, m) - np.outer(l, l))
+        ns.append(n)
+        Qs.append(Q)
+        Ss.append(S)
+    Qs = np.array(Qs)
+    q = np.stack([Qs[:, 0, 0], Qs[:, 0, 1], Qs[:, 0, 2], Qs[:, 1, 1], Qs[:, 1, 2]])
+    n, lam, w, defect = ora.directors(q, np.zeros(N, np.uint8), 0.3)
+    assert np.allclose(lam, Ss, rtol=0, atol=1e-14)
+    assert np.allclose(np.abs(np.einsum("in,ni->n", n, np.array(ns))), 1.0, atol=1e-12)
+    assert np.array_equal(defect, np.array(Ss) < 0.3)
+    # the sign convention: the largest component is positive
+    assert np.all(n[np.argmax(np.abs(n), axis=0), np.arange(N)] > 0)
+
+
+def test_director_special_sites(ora):
+    """Q = 0 has no director (n = 0, lambda = 0, a defect for any positive
+    threshold); object sites are never defects; an oblate uniaxial Q
+    (S < 0) has largest eigenvalue -S/2 and its director lies in the plane
+    normal to n."""
+    n0 = np.array([0.0, 0.6, 0.8])
+    S = -0.4
+    Q = 1.5 * S * (np.outer(n0, n0) - np.eye(3) / 3)
+    q = np.zeros((5, 3))
+    q[:, 2] = [Q[0, 0], Q[0, 1], Q[0, 2], Q[1, 1], Q[1, 2]]
+    q[:, 1] = 0.1
+    n, lam, w, defect = ora.directors(q, np.array([0, 2, 0], np.uint8), 0.05)
+    assert np.all(n[:, 0] == 0.0) and lam[0] == 0.0 and defect[0]
+    assert np.all(n[:, 1] == 0.0) and not defect[1]
+    assert abs(lam[2] + S / 2) <= 1e-15 and abs(n[:, 2] @ n0) <= 1e-12
