@@ -172,6 +172,20 @@ typedef struct {
 /* Discrete energy of q, summed in double in a fixed order. Synchronizes. */
 int lq_energy(lq_lattice* lat, const void* q, lq_energy_terms* out);
 
+/* Director and defect extraction (Eq. Qtensor and the text after it: the
+ * director is the eigenvector of Q for its largest eigenvalue, which equals
+ * S; the defect display of sec. IV: sites whose largest eigenvalue lies
+ * below a threshold).  Per simulated site: dirs (device, [3][N] elements of
+ * the lattice's type) receives the unit director with its largest-magnitude
+ * component positive (n and -n are one director), lambda_max (device, N
+ * elements) the largest eigenvalue, defect (device, N bytes) 1 where
+ * lambda_max < threshold.  Sites inside objects and sites with Q = 0 get a
+ * zero director and eigenvalue; object sites are never defects.  Any output
+ * may be NULL.  n_defects (host, may be NULL) receives the number of defect
+ * sites; the call then synchronizes.  Computed in FP64. */
+int lq_director_field(lq_lattice* lat, const void* q, void* dirs, void* lambda_max, uint8_t* defect,
+                      double threshold, int64_t* n_defects);
+
 /* ---- FIRE (Algorithm 1, after Bitzek et al. 2006) ---- */
 typedef struct {
     double dt0, dt_max;  /* initial and largest time step */

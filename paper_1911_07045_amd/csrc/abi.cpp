@@ -36,6 +36,7 @@ struct lq_lattice {
     EnergyOut* d_eout = nullptr;
     uint32_t* d_eticket = nullptr;
     EnergyOut* h_eout = nullptr;  // pinned
+    unsigned long long* h_count = nullptr;  // pinned: defect count
     // minimizer binding
     bool bound = false;
     int method = LQ_METHOD_FIRE;
@@ -258,6 +259,7 @@ int lq_lattice_create(const lq_params* p, void* stream, lq_lattice** out) {
             hipMalloc(&lat->d_eticket, 256) != hipSuccess ||
             hipHostMalloc(&lat->h_eout, sizeof(EnergyOut), hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc(&lat->h_state, sizeof(FireDev), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&lat->h_count, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
             hipMemset(lat->d_eticket, 0, 256) != hipSuccess) {
             (void)hipGetLastError();
             err = "device allocation failed";
@@ -283,6 +285,7 @@ int lq_lattice_destroy(lq_lattice* lat) {
     if (lat->d_eout) (void)hipFree(lat->d_eout);
     if (lat->d_eticket) (void)hipFree(lat->d_eticket);
     if (lat->h_eout) (void)hipHostFree(lat->h_eout);
+    if (lat->h_count) (void)hipHostFree(lat->h_count);
     if (lat->h_state) (void)hipHostFree(lat->h_state);
     delete lat;
     return LQ_OK;
@@ -384,6 +387,31 @@ int lq_energy(lq_lattice* lat, const void* q, lq_energy_terms* out) {
     out->external = lat->h_eout->ext;
     out->total = out->bulk + out->elastic + out->anchoring + out->external;
     out->n_sim = lat->n_sim;
+    return LQ_OK;
+}
+
+int lq_director_field(lq_lattice* lat, const void* q, void* dirs, void* lambda_max, uint8_t* defect,
+                      double threshold, int64_t* n_defects) {
+    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
+    if (!std::isfinite(threshold)) return fail(lat, LQ_EINVAL, "threshold is not finite");
+    int rc = check_dev_ptr(lat, q, "q");
+    if (rc == LQ_OK && dirs) rc = check_dev_ptr(lat, dirs, "dirs");
+    if (rc == LQ_OK && lambda_max) rc = check_dev_ptr(lat, lambda_max, "lambda_max");
+    if (rc == LQ_OK && defect) rc = check_dev_ptr(lat, defect, "defect");
+    if (rc != LQ_OK) return rc;
+    if (q == dirs || q == lambda_max || (dirs && dirs == lambda_max))
+        return fail(lat, LQ_EINVAL, "outputs must not alias q or each other");
+    HIPCHK(lat, hipSetDevice(lat->device));
+    // the defect counter sits in the energy kernel's ticket block, past the ticket
+    unsigned long long* d_count = n_defects ? (unsigned long long*)((char*)lat->d_eticket + 128) : nullptr;
+    rc = launch_directors(lat->dev, lat->p.prec, q, dirs, lambda_max, defect, threshold, d_count, lat->stream);
+    if (rc != LQ_OK) return fail(lat, rc, "kernel launch failed");
+    if (n_defects) {
+        HIPCHK(lat, hipMemcpyAsync(lat->h_count, d_count, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                   lat->stream));
+        HIPCHK(lat, hipStreamSynchronize(lat->stream));
+        *n_defects = (int64_t)*lat->h_count;
+    }
     return LQ_OK;
 }
 

@@ -1126,6 +1126,98 @@ __global__ __launch_bounds__(256) void k_energy(LatDev L, const T* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Director and defect extraction (Eq. Qtensor and the text after it; the
+// display of directors and defects in sec. IV): per simulated site the
+// largest eigenvalue of Q and its eigenvector, and whether that eigenvalue
+// lies below a threshold.  FP64 arithmetic.  For a traceless symmetric Q
+// with p = sqrt(tr(Q^2)/6) the eigenvalues are 2p cos((acos(r) + 2 pi m)/3),
+// r = det(Q)/(2 p^3) (the trigonometric solution of the characteristic
+// cubic), m = 0 giving the largest.  The eigenvector is the largest cross
+// product of two rows of Q - lambda I; when Q - lambda I has rank one (the
+// largest eigenvalue is doubly degenerate) any vector normal to its
+// non-zero row is an eigenvector.  n and -n being equal, the sign makes the
+// largest-magnitude component positive.
+template <typename T>
+__global__ __launch_bounds__(256) void k_directors(LatDev L, const T* __restrict__ q, T* __restrict__ dirs,
+                                                   T* __restrict__ lmax, uint8_t* __restrict__ defect,
+                                                   double thr, unsigned long long* count) {
+    __shared__ unsigned int block_count;
+    if (threadIdx.x == 0) block_count = 0;
+    __syncthreads();
+    const int64_t N = L.N;
+    unsigned int mine = 0;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < N;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        double n[3] = {0.0, 0.0, 0.0}, lam = 0.0;
+        const bool sim = (L.mask[s] & M_SIM) != 0;
+        if (sim) {
+            double v[5];
+            for (int c = 0; c < 5; ++c) v[c] = (double)q[c * N + s];
+            double Q[3][3];
+            full_of(v, Q);
+            double p2 = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) p2 += Q[i][j] * Q[i][j];
+            if (p2 > 0.0) {
+                const double p = sqrt(p2 / 6.0);
+                const double det = Q[0][0] * (Q[1][1] * Q[2][2] - Q[1][2] * Q[2][1]) -
+                                   Q[0][1] * (Q[1][0] * Q[2][2] - Q[1][2] * Q[2][0]) +
+                                   Q[0][2] * (Q[1][0] * Q[2][1] - Q[1][1] * Q[2][0]);
+                const double r = fmin(1.0, fmax(-1.0, det / (2.0 * p * p * p)));
+                lam = 2.0 * p * cos(acos(r) / 3.0);
+                double A[3][3];
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) A[i][j] = Q[i][j] - (i == j ? lam : 0.0);
+                double best = -1.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = a + 1; b < 3; ++b) {
+                        const double c[3] = {A[a][1] * A[b][2] - A[a][2] * A[b][1],
+                                             A[a][2] * A[b][0] - A[a][0] * A[b][2],
+                                             A[a][0] * A[b][1] - A[a][1] * A[b][0]};
+                        const double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+                        if (c2 > best) { best = c2; n[0] = c[0]; n[1] = c[1]; n[2] = c[2]; }
+                    }
+                if (!(best > 0.0)) {
+                    // rank one: a vector normal to the largest row
+                    int a = 0;
+                    double rb = -1.0;
+                    for (int i = 0; i < 3; ++i) {
+                        const double r2 = A[i][0] * A[i][0] + A[i][1] * A[i][1] + A[i][2] * A[i][2];
+                        if (r2 > rb) { rb = r2; a = i; }
+                    }
+                    int e = 0;
+                    for (int k = 1; k < 3; ++k)
+                        if (fabs(A[a][k]) < fabs(A[a][e])) e = k;
+                    double u[3] = {0.0, 0.0, 0.0};
+                    u[e] = 1.0;
+                    n[0] = A[a][1] * u[2] - A[a][2] * u[1];
+                    n[1] = A[a][2] * u[0] - A[a][0] * u[2];
+                    n[2] = A[a][0] * u[1] - A[a][1] * u[0];
+                    best = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+                }
+                const double inv = best > 0.0 ? 1.0 / sqrt(best) : 0.0;
+                int big = 0;
+                for (int k = 1; k < 3; ++k)
+                    if (fabs(n[k]) > fabs(n[big])) big = k;
+                const double sg = n[big] < 0.0 ? -inv : inv;
+                for (int k = 0; k < 3; ++k) n[k] *= sg;
+            }
+        }
+        const bool is_defect = sim && lam < thr;
+        mine += is_defect ? 1u : 0u;
+        if (dirs)
+            for (int k = 0; k < 3; ++k) dirs[k * N + s] = T(n[k]);
+        if (lmax) lmax[s] = T(lam);
+        if (defect) defect[s] = is_defect ? 1 : 0;
+    }
+    if (count) {
+        atomicAdd(&block_count, mine);
+        __syncthreads();
+        if (threadIdx.x == 0 && block_count) atomicAdd(count, (unsigned long long)block_count);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 static int hip_status(hipError_t e) { return e == hipSuccess ? LQ_OK : LQ_EHIP; }
 
@@ -1209,6 +1301,21 @@ int launch_lookahead(const LatDev& L, int prec, const void* q, const void* m, do
         k_lookahead<double><<<grid_1d(n), 256, 0, s>>>((const double*)q, (const double*)m, mu, (double*)y, n);
     else
         k_lookahead<float><<<grid_1d(n), 256, 0, s>>>((const float*)q, (const float*)m, (float)mu, (float*)y, n);
+    return hip_status(hipGetLastError());
+}
+
+int launch_directors(const LatDev& L, int prec, const void* q, void* dirs, void* lmax, uint8_t* defect,
+                     double thr, unsigned long long* count, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (count) {
+        k_fill_zero<<<1, 64, 0, s>>>((uint32_t*)count, 2);
+        if (hipGetLastError() != hipSuccess) return LQ_EHIP;
+    }
+    const int g = grid_1d(L.N);
+    if (prec == LQ_F64)
+        k_directors<double><<<g, 256, 0, s>>>(L, (const double*)q, (double*)dirs, (double*)lmax, defect, thr, count);
+    else
+        k_directors<float><<<g, 256, 0, s>>>(L, (const float*)q, (float*)dirs, (float*)lmax, defect, thr, count);
     return hip_status(hipGetLastError());
 }
 

@@ -117,6 +117,8 @@ int launch_finalize(const LatDev& L, int prec, bool with_v, const void* bufs, Fi
 int launch_lookahead(const LatDev& L, int prec, const void* q, const void* m, double mu, void* y,
                      void* stream);
 int launch_fill_zero(void* p, int64_t bytes, void* stream);
+int launch_directors(const LatDev& L, int prec, const void* q, void* dirs, void* lmax, uint8_t* defect,
+                     double thr, unsigned long long* count, void* stream);
 int launch_energy(const LatDev& L, bool l23, int prec, const void* q, double* partials,
                   EnergyOut* out, uint32_t* ticket, void* stream);
 int launch_uniaxial(const LatDev& L, int prec, const double* dirs, double S, void* q,

@@ -113,6 +113,7 @@ def lib():
                                           C.POINTER(FireReport)]),
             "lq_descent_minimize": (C.c_int, [vp, C.POINTER(DescentParams), vp, vp, vp, vp, i64,
                                               C.POINTER(FireReport)]),
+            "lq_director_field": (C.c_int, [vp, vp, vp, vp, vp, C.c_double, C.POINTER(C.c_int64)]),
             "lq_last_error": (C.c_char_p, [vp]),
             "lq_batch_create": (C.c_int, [i32, vp, C.POINTER(vp)]),
             "lq_batch_destroy": (C.c_int, [vp]),
@@ -317,6 +318,22 @@ class Lattice:
         return {"bulk": out.bulk, "elastic": out.elastic, "anchoring": out.anchoring,
                 "external": out.external, "total": out.total, "n_sim": out.n_sim}
 
+    def director_field(self, q, threshold, dirs=None, lambda_max=None, defect=None):
+        """(dirs [3, N...], lambda_max [N...], defect [N...] uint8, n_defects) of q."""
+        torch = self.torch
+        shp = tuple(q.shape[1:])
+        dirs = torch.empty((3,) + shp, dtype=self.dtype, device=self.device) if dirs is None else dirs
+        lam = torch.empty(shp, dtype=self.dtype, device=self.device) if lambda_max is None else lambda_max
+        dfc = torch.empty(shp, dtype=torch.uint8, device=self.device) if defect is None else defect
+        for t, n, dt in ((dirs, 3 * self.N, self.dtype), (lam, self.N, self.dtype), (dfc, self.N, torch.uint8)):
+            if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.numel() == n and t.device == self.device):
+                raise ValueError("director outputs must be contiguous CUDA tensors of the lattice's size")
+        n = C.c_int64(0)
+        _check(lib().lq_director_field(self.h, self._field(q, "q"), C.c_void_p(dirs.data_ptr()),
+                                       C.c_void_p(lam.data_ptr()), C.c_void_p(dfc.data_ptr()),
+                                       float(threshold), C.byref(n)), self.h)
+        return dirs, lam, dfc, n.value
+
     def workspace_bytes(self):
         return int(lib().lq_workspace_bytes(self.h))
 
@@ -444,6 +461,10 @@ def fire_step(lat: Lattice, n_steps):
 
 def minimize(lat: Lattice, params, q, v=None, F=None):
     return lat.minimize(params, q, v, F)
+
+
+def director_field(lat: Lattice, q, threshold):
+    return lat.director_field(q, threshold)
 
 
 def descent_minimize(lat: Lattice, params, q, v=None, F=None):

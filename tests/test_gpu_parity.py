@@ -591,3 +591,86 @@ def test_full_size_fused_step_consistency(ora):
     dt0 = cfg["fire"]["dt0"]
     ref = 0.5 * dt0 * dt0 * F0
     assert np.abs(dq - ref).max() <= 2e-7 * np.abs(q0h).max() + 1e-5 * np.abs(ref).max()
+
+
+def _check_directors(ora, p, q64, dirs, lam, dfc, n_def, thr, tol):
+    n_o, lam_o, w_o, def_o = ora.directors(q64.reshape(5, -1), p.types, thr)
+    dirs = dirs.reshape(3, -1).astype(np.float64)
+    lam = lam.reshape(-1).astype(np.float64)
+    dfc = dfc.reshape(-1)
+    scale = max(1.0, np.abs(lam_o).max())
+    assert np.abs(lam - lam_o).max() <= tol * scale
+    sim = p.types != 2
+    gap = w_o[:, 2] - w_o[:, 1]
+    clear = sim & (gap > 1e-6 * scale)
+    # a simple largest eigenvalue: the director is unique up to sign, and the
+    # sign convention fixes it where the largest component is clear
+    dots = np.abs(np.einsum("in,in->n", dirs[:, clear], n_o[:, clear]))
+    assert np.all(dots >= 1.0 - 10 * tol)
+    a = np.sort(np.abs(n_o[:, clear]), axis=0)
+    sep = a[2] - a[1] > 1e-6
+    assert np.abs(dirs[:, clear][:, sep] - n_o[:, clear][:, sep]).max() <= 1e3 * tol
+    # elsewhere any unit eigenvector of the largest eigenvalue is right
+    Q = ora.director.full_Q(q64.reshape(5, -1))
+    rest = sim & ~clear & (lam_o != 0.0)
+    if rest.any():
+        res = np.einsum("nij,jn->in", Q[rest], dirs[:, rest]) - lam_o[rest] * dirs[:, rest]
+        assert np.abs(res).max() <= 1e3 * tol * scale
+        assert np.allclose((dirs[:, rest] ** 2).sum(axis=0), 1.0, atol=1e3 * tol)
+    assert np.all(dirs[:, ~sim] == 0.0) and np.all(lam[~sim] == 0.0)
+    borderline = np.abs(lam_o - thr) <= 1e3 * tol * scale
+    assert np.array_equal(dfc[~borderline].astype(bool), def_o[~borderline])
+    assert n_def == int(dfc.sum())
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_director_field_matches_oracle(ora, prec):
+    """Largest eigenvalue, director and defect mask of a generic (biaxial)
+    field with objects, zero sites, exactly uniaxial prolate and oblate
+    sites, against numpy's eigh in the oracle."""
+    say(f"[directors] {prec}")
+    c = CASES["colloid_slab24_L23"]
+    p, lat = pair(ora, c["shape"], objects=c["objects"], prec=prec)
+    q = synth.random_field(21, p.N).reshape(5, -1)
+    n0 = np.array([0.0, 0.6, 0.8])
+    for site, S in ((1000, 0.5), (1001, -0.4), (1002, 0.0)):
+        Qs = 1.5 * S * (np.outer(n0, n0) - np.eye(3) / 3)
+        q[:, site] = [Qs[0, 0], Qs[0, 1], Qs[0, 2], Qs[1, 1], Qs[1, 2]]
+    Qd = np.diag([0.2, 0.2, -0.4])
+    q[:, 1003] = [Qd[0, 0], 0.0, 0.0, Qd[1, 1], 0.0]
+    q[:, p.types == 2] = 0.0
+    if prec == "f32":
+        q = q.astype(np.float32).astype(np.float64)
+    q = q.reshape(p.field_shape)
+    qd = to_dev(q, torch.float64 if prec == "f64" else torch.float32)
+    thr = 0.1
+    dirs, lam, dfc, n_def = lat.director_field(qd, thr)
+    tol = 1e-12 if prec == "f64" else 2e-7
+    _check_directors(ora, p, q, dirs.cpu().numpy(), lam.cpu().numpy(), dfc.cpu().numpy(), n_def, thr, tol)
+    assert 0 < n_def < p.n_sim
+
+
+def test_director_field_of_a_hedgehog():
+    """A radial hedgehog n = r/|r| with S(r) = S0 tanh(|r|/2) around the box
+    centre: lambda_max = S(r) at every site and the director is radial, so
+    the defect sites are exactly those with S(r) below the threshold."""
+    say("[directors] hedgehog")
+    shape = (33, 30, 31)
+    lat = lqfire.Lattice(shape, prec="f64")
+    nx, ny, nz = shape
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.stack([X - 16.3, Y - 14.6, Z - 15.2]).reshape(3, -1).astype(np.float64)
+    rad = np.sqrt((r * r).sum(axis=0))
+    n = r / rad
+    S = lat.S0 * np.tanh(rad / 2.0)
+    q = np.stack([1.5 * S * (n[0] * n[0] - 1 / 3), 1.5 * S * n[0] * n[1], 1.5 * S * n[0] * n[2],
+                  1.5 * S * (n[1] * n[1] - 1 / 3), 1.5 * S * n[1] * n[2]]).reshape(lat.field_shape)
+    thr = 0.5 * lat.S0
+    dirs, lam, dfc, n_def = lat.director_field(to_dev(q, torch.float64), thr)
+    lam = lam.cpu().numpy().reshape(-1)
+    dirs = dirs.cpu().numpy().reshape(3, -1)
+    assert np.abs(lam - S).max() <= 1e-12
+    assert np.abs(np.abs((dirs * n).sum(axis=0)) - 1.0).max() <= 1e-12
+    clear = np.abs(S - thr) > 1e-9
+    assert np.array_equal(dfc.cpu().numpy().reshape(-1)[clear].astype(bool), (S < thr)[clear])
+    assert n_def == int((S < thr).sum()) and n_def > 0
