@@ -135,20 +135,29 @@ static int check_dev_ptr(lq_lattice* lat, const void* ptr, const char* name) {
 }
 
 // z-chunk per block: as long as possible while the grid keeps >= 2048 blocks
-static int pick_zc(const lq_params& p) {
+// Planes per block: the longest march (at most 64 planes, so the two halo
+// planes cost at most 1/32 of the traffic) that still gives every compute
+// unit its full complement of resident blocks.
+static int pick_zc(const lq_params& p, int device, bool l23) {
     const char* env = std::getenv("LQ_ZC");
     if (env) {
         int z = std::atoi(env);
         if (z >= 1 && z <= 4096) return z;
     }
-    int64_t ntx = (p.n[0] + TX - 1) / TX, nty = (p.n[1] + TY - 1) / TY;
-    int zc = 32;
-    while (zc > 4 && ntx * nty * ((p.n[2] + zc - 1) / zc) < 2048) zc /= 2;
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n_cu <= 0)
+        n_cu = 256;
+    const int64_t resident = (int64_t)n_cu * step_blocks_per_cu(p.prec, l23);
+    const int tx = tile_x(p.prec), ty = tile_y(p.prec);
+    const int64_t ntx = (p.n[0] + tx - 1) / tx, nty = (p.n[1] + ty - 1) / ty;
+    int zc = 64;
+    while (zc > 4 && ntx * nty * ((p.n[2] + zc - 1) / zc) < resident) zc /= 2;
     return zc;
 }
 
 static void tile_flags(const lq_params& p, const std::vector<uint8_t>& mask, int zc, int ntx, int nty,
                        int ntz, std::vector<uint8_t>& out) {
+    const int64_t TX = tile_x(p.prec), TY = tile_y(p.prec);
     const int64_t nx = p.n[0], ny = p.n[1], nz = p.n[2];
     out.assign((size_t)ntx * nty * ntz, 0);
     auto wrap = [](int64_t g, int64_t n, bool per) -> int64_t {
@@ -199,9 +208,9 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     for (int k = 0; k < 3; ++k) d.per[k] = p.periodic[k];
     d.N = lat->N;
     d.A = p.A; d.B = p.B; d.C = p.C; d.L1 = p.L1; d.L2 = p.L2; d.L3 = p.L3; d.L4 = p.L4;
-    d.zc = pick_zc(p);
-    d.ntx = (int)((p.n[0] + TX - 1) / TX);
-    d.nty = (int)((p.n[1] + TY - 1) / TY);
+    d.zc = pick_zc(p, lat->device, lat->l23);
+    d.ntx = (int)((p.n[0] + tile_x(p.prec) - 1) / tile_x(p.prec));
+    d.nty = (int)((p.n[1] + tile_y(p.prec) - 1) / tile_y(p.prec));
     d.ntz = (int)((p.n[2] + d.zc - 1) / d.zc);
     std::vector<uint8_t> tiles;
     tile_flags(p, g.mask, d.zc, d.ntx, d.nty, d.ntz, tiles);

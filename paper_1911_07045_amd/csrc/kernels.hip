@@ -28,7 +28,7 @@
 // block to finish (atomic ticket), which then runs the controller.  The host
 // never waits between steps.
 //
-// Layout: SoA fields [5][nz][ny][nx].  A block owns a TX x TY column tile and
+// Layout: SoA fields [5][nz][ny][nx].  A block owns an X x Y column tile and
 // marches zc planes along z, keeping the drifted q of four planes with their
 // halo in LDS: the force of plane f reads planes f-1, f, f+1 while plane f+1
 // is being written, so that one barrier per plane suffices.
@@ -38,8 +38,6 @@
 
 namespace lq {
 
-constexpr int PX = TX + 2;
-constexpr int PY = TY + 2;
 
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
@@ -59,13 +57,22 @@ __device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
     }
 }
+// Stores of the streamed fields carry the non-temporal cache policy (bit 1
+// of the buffer instruction's cache-policy operand on gfx950): the next
+// step reads them back from HBM, so they should not displace the reused
+// lines of the current step.
+#ifndef LQ_STORE_POLICY
+#define LQ_STORE_POLICY 2
+#endif
 template <typename T>
 __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v) {
     if constexpr (sizeof(T) == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff,
+                                              LQ_STORE_POLICY);
     } else {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff,
+                                              LQ_STORE_POLICY);
     }
 }
 
@@ -247,8 +254,8 @@ __device__ __forceinline__ void chiral_nb(int k, const T qx[5], T h[5]) {
 // neighbours, so masks are compile-time constants.
 template <typename T, bool L23, bool BULK>
 struct Stencil {
-    T (*q)[5][PY][PX];
-    uint8_t (*m)[PY][PX];
+    T (*q)[5][Tile<T>::PY][Tile<T>::PX];
+    uint8_t (*m)[Tile<T>::PY][Tile<T>::PX];
     int s[3];  // LDS slots of the planes below, at and above the centre
     int cx, cy;
     __device__ __forceinline__ T at(int dx, int dy, int dz, int c) const {
@@ -451,10 +458,13 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Block reduction of 4 values (3 sums, 1 max) in a fixed order.
+// Block reduction of 4 values in a fixed order: 3 sums and a max
+// (LAST_MAX, the step partials), or 4 sums (the energy terms).
+template <bool LAST_MAX = true>
 __device__ __forceinline__ void block_reduce4(double r[4], double (*scratch)[4]) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double a = wave_sum(r[0]), b = wave_sum(r[1]), c = wave_sum(r[2]), d = wave_max(r[3]);
+    double a = wave_sum(r[0]), b = wave_sum(r[1]), c = wave_sum(r[2]);
+    double d = LAST_MAX ? wave_max(r[3]) : wave_sum(r[3]);
     if (lane == 0) {
         scratch[wv][0] = a; scratch[wv][1] = b; scratch[wv][2] = c; scratch[wv][3] = d;
     }
@@ -464,7 +474,7 @@ __device__ __forceinline__ void block_reduce4(double r[4], double (*scratch)[4])
         double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
         for (int w = 0; w < nw; ++w) {
             s0 += scratch[w][0]; s1 += scratch[w][1]; s2 += scratch[w][2];
-            s3 = fmax(s3, scratch[w][3]);
+            s3 = LAST_MAX ? fmax(s3, scratch[w][3]) : s3 + scratch[w][3];
         }
         r[0] = s0; r[1] = s1; r[2] = s2; r[3] = s3;
     }
@@ -560,18 +570,16 @@ __device__ void grid_finish(double r[4], double* partials, FireDev* st, int nblo
 //   Nesterov  m' = mu m + dt F, q' = q + m', F' = F(q' + mu m')  (m in the
 //             v buffers; the stencil holds the look-ahead point q' + mu m').
 //
-// A block owns a TX x TY column tile and the planes z0 .. z0+zc-1.  Plane i
+// A block owns an X x Y column tile and the planes z0 .. z0+zc-1.  Plane i
 // of the march (global z = z0 - 1 + i, i = 0 .. zc+1) is loaded into
 // registers (the block's own sites, plus the one-site ring around the tile
 // spread over all threads one (site, component) pair at a time), then drifted
 // (steering, first half kick, q += dt v) into an LDS slot.  Loads run one
 // plane ahead of the drift, so the loads of plane i+1 are in flight while the
 // force of plane i-1 is evaluated.
-constexpr int RING = 2 * PX + 2 * (PY - 2);
-constexpr int RING_ITEMS = 5 * RING;
-constexpr int ITEMS_PER_THREAD = (RING_ITEMS + NTHREADS - 1) / NTHREADS;
-
+template <typename T>
 __device__ __forceinline__ void ring_pos(int r, int& px, int& py) {
+    constexpr int PX = Tile<T>::PX, PY = Tile<T>::PY;
     if (r < PX) { px = r; py = 0; }
     else if (r < 2 * PX) { px = r - PX; py = PY - 1; }
     else if (r < 2 * PX + PY - 2) { px = 0; py = r - 2 * PX + 1; }
@@ -583,9 +591,11 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                                       const T* __restrict__ v_in, const T* __restrict__ F_in,
                                       T* __restrict__ q_out, T* __restrict__ v_out,
                                       T* __restrict__ F_out, T cv, T cF, T dt, T hdt, int x0, int y0,
-                                      int z0, int zc, T (*sq)[5][PY][PX], uint8_t (*sm)[PY][PX],
-                                      double red[4]) {
+                                      int z0, int zc, T (*sq)[5][Tile<T>::PY][Tile<T>::PX],
+                                      uint8_t (*sm)[Tile<T>::PY][Tile<T>::PX], double red[4]) {
     constexpr int NS = 4;
+    constexpr int TX = Tile<T>::X, NTHREADS = Tile<T>::N, RING = Tile<T>::RING;
+    constexpr int RING_ITEMS = Tile<T>::RING_ITEMS, ITEMS_PER_THREAD = Tile<T>::IPT;
     constexpr bool STEP = MODE != MODE_FORCE;
     constexpr bool USES_V = MODE == MODE_FIRE || MODE == MODE_NAG;
     const int64_t N = L.N;
@@ -606,7 +616,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
         it_c[j] = -1; it_px[j] = 0; it_py[j] = 0; it_sxy[j] = -1;
         if (k < RING_ITEMS) {
             it_c[j] = k / RING;
-            ring_pos(k % RING, it_px[j], it_py[j]);
+            ring_pos<T>(k % RING, it_px[j], it_py[j]);
             const int wx = wrapc(x0 - 1 + it_px[j], L.nx, L.per[0]);
             const int wy = wrapc(y0 - 1 + it_py[j], L.ny, L.per[1]);
             it_sxy[j] = (wx >= 0 && wy >= 0) ? wx + L.nx * wy : -1;
@@ -782,9 +792,10 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
                                            T* __restrict__ Fout, double* partials, FireDev* st,
                                            int nblocks, int bid) {
     constexpr int NS = 4;
+    constexpr int TX = Tile<T>::X, TY = Tile<T>::Y, PX = Tile<T>::PX, PY = Tile<T>::PY;
     __shared__ T sq[NS][5][PY][PX];
     __shared__ uint8_t sm[NS][PY][PX];
-    __shared__ double scratch[NTHREADS / 64][4];
+    __shared__ double scratch[Tile<T>::N / 64][4];
     __shared__ int last_flag;
 
     const int bx = bid % L.ntx, by = (bid / L.ntx) % L.nty, bz = bid / (L.ntx * L.nty);
@@ -798,8 +809,9 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
     if (STEP) {
         if (st->done) return;
         const int cur = st->cur;
-        q_in = b.q[cur]; v_in = b.v[cur]; F_in = b.F[cur];
-        q_out = b.q[1 - cur]; v_out = b.v[1 - cur]; F_out = b.F[1 - cur];
+        // selects rather than indexing by cur, which would put b in scratch
+        q_in = cur ? b.q[1] : b.q[0]; v_in = cur ? b.v[1] : b.v[0]; F_in = cur ? b.F[1] : b.F[0];
+        q_out = cur ? b.q[0] : b.q[1]; v_out = cur ? b.v[0] : b.v[1]; F_out = cur ? b.F[0] : b.F[1];
         const double dtd = st->dt;
         dt = T(dtd); hdt = T(0.5 * dtd);
         if (MODE == MODE_FIRE) { cv = T(st->c_v); cF = T(st->c_F); }
@@ -819,7 +831,7 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
 }
 
 template <typename T, bool L23, int MODE>
-__global__ __launch_bounds__(NTHREADS) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
+__global__ __launch_bounds__(Tile<T>::N) __attribute__((amdgpu_waves_per_eu(L23 ? 1 : Tile<T>::WAVES))) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
                                                     T* __restrict__ Fout, double* partials,
                                                     FireDev* st) {
     const int nblocks = (int)gridDim.x;
@@ -844,7 +856,7 @@ __device__ __forceinline__ int member_of(const int* __restrict__ off, int n, int
 }
 
 template <typename T, bool L23>
-__global__ __launch_bounds__(NTHREADS) void k_march_batch(const MemberDev* __restrict__ mem,
+__global__ __launch_bounds__(Tile<T>::N) __attribute__((amdgpu_waves_per_eu(L23 ? 1 : Tile<T>::WAVES))) void k_march_batch(const MemberDev* __restrict__ mem,
                                                           const int* __restrict__ off, int n_members) {
     const int m = member_of(off, n_members, (int)blockIdx.x);
     const MemberDev& M = mem[m];
@@ -853,7 +865,7 @@ __global__ __launch_bounds__(NTHREADS) void k_march_batch(const MemberDev* __res
     for (int i = 0; i < 2; ++i) {
         b.q[i] = (T*)M.q[i]; b.v[i] = (T*)M.v[i]; b.F[i] = (T*)M.F[i];
     }
-    const LatDev L = M.L;
+    const LatDev& L = M.L;
     step_block<T, L23, MODE_FIRE>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
                              (int)blockIdx.x - off[m]);
 }
@@ -1100,7 +1112,7 @@ __global__ __launch_bounds__(256) void k_energy(LatDev L, const T* __restrict__ 
         }
     }
     double r[4] = {e_b, e_d, e_a, e_x};
-    block_reduce4(r, scratch);
+    block_reduce4<false>(r, scratch);
     if (threadIdx.x == 0) {
         double* p = partials + 4 * (int64_t)blockIdx.x;
         p[0] = r[0]; p[1] = r[1]; p[2] = r[2]; p[3] = r[3];
@@ -1117,7 +1129,7 @@ __global__ __launch_bounds__(256) void k_energy(LatDev L, const T* __restrict__ 
         s4[0] += p[0]; s4[1] += p[1]; s4[2] += p[2]; s4[3] += p[3];
     }
     __syncthreads();
-    block_reduce4(s4, scratch);
+    block_reduce4<false>(s4, scratch);
     if (threadIdx.x == 0) {
         out->bulk = s4[0]; out->elastic = s4[1]; out->anch = s4[2]; out->ext = s4[3];
         *ticket = 0;
@@ -1222,6 +1234,19 @@ __global__ __launch_bounds__(256) void k_directors(LatDev L, const T* __restrict
 static int hip_status(hipError_t e) { return e == hipSuccess ? LQ_OK : LQ_EHIP; }
 
 int64_t n_step_blocks(const LatDev& L) { return (int64_t)L.ntx * L.nty * L.ntz; }
+
+// Resident blocks per compute unit of the fused FIRE step kernel.
+int step_blocks_per_cu(int prec, bool l23) {
+    int n = 0;
+    hipError_t e;
+    if (prec == LQ_F64)
+        e = l23 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<double, true, MODE_FIRE>, Tile<double>::N, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<double, false, MODE_FIRE>, Tile<double>::N, 0);
+    else
+        e = l23 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<float, true, MODE_FIRE>, Tile<float>::N, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<float, false, MODE_FIRE>, Tile<float>::N, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
 int64_t n_energy_blocks(const LatDev& L) {
     int64_t b = (L.N + 255) / 256;
     return b < 2048 ? b : 2048;
@@ -1233,7 +1258,7 @@ static int grid_1d(int64_t n) {
 }
 
 int launch_forces(const LatDev& L, bool l23, int prec, const void* q, void* F, void* stream) {
-    dim3 g((unsigned)n_step_blocks(L)), blk(NTHREADS);
+    dim3 g((unsigned)n_step_blocks(L)), blk(prec == LQ_F64 ? Tile<double>::N : Tile<float>::N);
     hipStream_t s = (hipStream_t)stream;
     if (prec == LQ_F64) {
         Bufs<double> b{};
@@ -1263,7 +1288,7 @@ static void launch_step(const LatDev& L, bool l23, int prec, const void* bufs, d
 
 int launch_fire_steps(const LatDev& L, bool l23, int prec, int method, const void* bufs, double* partials,
                       FireDev* st, int64_t n_steps, void* stream) {
-    dim3 g((unsigned)n_step_blocks(L)), blk(NTHREADS);
+    dim3 g((unsigned)n_step_blocks(L)), blk(prec == LQ_F64 ? Tile<double>::N : Tile<float>::N);
     hipStream_t s = (hipStream_t)stream;
     for (int64_t i = 0; i < n_steps; ++i) {
         if (method == LQ_METHOD_GD) launch_step<MODE_GD>(L, l23, prec, bufs, partials, st, g, blk, s);
@@ -1356,11 +1381,11 @@ int launch_batch_steps(int prec, bool l23, const MemberDev* mem, const int* tile
     if (hipGetLastError() != hipSuccess) return LQ_EHIP;
     for (int64_t i = 0; i < n_steps; ++i) {
         if (prec == LQ_F64) {
-            if (l23) k_march_batch<double, true><<<total_tiles, NTHREADS, 0, s>>>(mem, tile_off, n_members);
-            else k_march_batch<double, false><<<total_tiles, NTHREADS, 0, s>>>(mem, tile_off, n_members);
+            if (l23) k_march_batch<double, true><<<total_tiles, Tile<double>::N, 0, s>>>(mem, tile_off, n_members);
+            else k_march_batch<double, false><<<total_tiles, Tile<double>::N, 0, s>>>(mem, tile_off, n_members);
         } else {
-            if (l23) k_march_batch<float, true><<<total_tiles, NTHREADS, 0, s>>>(mem, tile_off, n_members);
-            else k_march_batch<float, false><<<total_tiles, NTHREADS, 0, s>>>(mem, tile_off, n_members);
+            if (l23) k_march_batch<float, true><<<total_tiles, Tile<float>::N, 0, s>>>(mem, tile_off, n_members);
+            else k_march_batch<float, false><<<total_tiles, Tile<float>::N, 0, s>>>(mem, tile_off, n_members);
         }
         if (hipGetLastError() != hipSuccess) return LQ_EHIP;
     }

@@ -36,17 +36,47 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
               const lq_site_anchor* recs, int64_t n_recs, const int64_t* object_sites,
               int64_t n_object_sites, Geometry& g, std::string& err);
 
-// Tile geometry of the fused kernel: TX x TY columns, each block marches
-// zc planes.
-#ifndef LQ_TILE_X
-#define LQ_TILE_X 32
+// Tile geometry of the fused kernel, per element type: a block of X x Y
+// threads owns an X x Y column tile and marches zc planes along z.  Wider
+// rows give longer contiguous runs per wave; the FP64 tile is narrower so
+// that two blocks still fit the LDS of a compute unit.
+#ifndef LQ_TILE_X_F32
+#define LQ_TILE_X_F32 64
 #endif
-#ifndef LQ_TILE_Y
-#define LQ_TILE_Y 8
+#ifndef LQ_TILE_Y_F32
+#define LQ_TILE_Y_F32 8
 #endif
-constexpr int TX = LQ_TILE_X;
-constexpr int TY = LQ_TILE_Y;
-constexpr int NTHREADS = TX * TY;
+#ifndef LQ_TILE_X_F64
+#define LQ_TILE_X_F64 32
+#endif
+#ifndef LQ_TILE_Y_F64
+#define LQ_TILE_Y_F64 8
+#endif
+template <int TX_, int TY_>
+struct TileGeom {
+    static constexpr int X = TX_, Y = TY_;
+    static constexpr int N = X * Y;            // threads per block
+    static constexpr int PX = X + 2, PY = Y + 2;  // padded tile in LDS
+    static constexpr int RING = 2 * PX + 2 * (PY - 2);
+    static constexpr int RING_ITEMS = 5 * RING;   // (site, component) pairs of the ring
+    static constexpr int IPT = (RING_ITEMS + N - 1) / N;
+};
+template <typename T>
+struct Tile;
+// WAVES: waves per SIMD the one-constant (L1) step kernels are held to
+// (register budget 512 / WAVES), so that two FP32 blocks share a compute
+// unit; the L2/L3 kernels need more registers than that allows without
+// spilling and are left unconstrained.
+template <>
+struct Tile<float> : TileGeom<LQ_TILE_X_F32, LQ_TILE_Y_F32> {
+    static constexpr int WAVES = 4;
+};
+template <>
+struct Tile<double> : TileGeom<LQ_TILE_X_F64, LQ_TILE_Y_F64> {
+    static constexpr int WAVES = 1;
+};
+inline int tile_x(int prec) { return prec == LQ_F64 ? Tile<double>::X : Tile<float>::X; }
+inline int tile_y(int prec) { return prec == LQ_F64 ? Tile<double>::Y : Tile<float>::Y; }
 
 // Device view of a lattice.
 struct LatDev {
@@ -127,6 +157,7 @@ int launch_batch_steps(int prec, bool l23, const MemberDev* mem, const int* tile
                        int total_tiles, const int* fin_off, int total_fin, FireDev* gather, int64_t n_steps,
                        void* stream);
 int64_t n_step_blocks(const LatDev& L);
+int step_blocks_per_cu(int prec, bool l23);
 int64_t n_energy_blocks(const LatDev& L);
 
 }  // namespace lq

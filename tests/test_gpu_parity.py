@@ -283,7 +283,7 @@ def _descent_trajectory(ora, p, lat, q0, method, dt, mu, steps, every, tol, prec
         assert np.abs(q.cpu().numpy() - qo).max() <= tol * max(1.0, np.abs(qo).max())
         if method == "nesterov":
             assert np.abs(v.cpu().numpy() - mo).max() <= tol * max(1e-3, np.abs(mo).max())
-            assert abs(rep.P - st.P) <= 1e-8 * abs(st.normF * st.normv) + 1e-300
+            assert abs(rep.P - st.P) <= max(1e-8, tol) * abs(st.normF * st.normv) + 1e-300
         assert rep.step == st.step and rep.status == st.status
         assert rep.normF == pytest.approx(st.normF, rel=max(tol, 1e-9))
     return rep, st
