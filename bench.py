@@ -253,6 +253,39 @@ def serving_leg(n_requests=512, rate=20.0):
 
 
 COPY_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_fire_f32_multi_colloid256_hbm.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_07045_amd", "csrc", f) for f in ("kernels.hip", "lq_internal.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per step-kernel launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or None when
+    the summary is for another workload or the kernel source has changed
+    since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("workload") != workload_name or vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def copy_calibration(reps=5):
@@ -282,9 +315,14 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--no-minimizers", action="store_true",
                     help="skip the gradient-descent / Nesterov step timings")
+    ap.add_argument("--kernel-hash", action="store_true",
+                    help="print the hash of the kernel sources that a counter summary records")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of a known size (HBM counter scale)")
     args = ap.parse_args()
+    if args.kernel_hash:
+        print(kernel_source_hash())
+        return
     if args.copy_calibration:
         copy_calibration()
         return
@@ -316,7 +354,7 @@ def main():
         "config": describe(cfg),
         "simulated_site_updates_per_s": g["n_sim"] * args.steps / g["wall_s"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["name"]),
                      "kernel": "k_march<fused FIRE step>", "kernel_ms": g["kernel_ms"],
                      "algorithmic_bytes_per_launch": alg_bytes},
         "energy_start_end": [g["E0"], g["E1"]],
