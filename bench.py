@@ -46,6 +46,8 @@ def workload(name):
         return synth.patterned_wall(512)
     if name == "bulk32":
         return synth.bulk32()
+    if name == "bulk256":
+        return synth.bulk(256)
     raise SystemExit(f"unknown workload {name}")
 
 

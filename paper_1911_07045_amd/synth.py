@@ -99,6 +99,15 @@ def bulk32(seed=0):
                 fire=dict(FIRE, force_tol=1e-9, max_steps=2000))
 
 
+def bulk(n=256, seed=0, prec="f32"):
+    """n^3 periodic bulk box from random directors, one-constant L1 (the
+    setting of the paper's FIRE-vs-gradient-descent comparison, a 250^3 bulk
+    box)."""
+    return dict(name=f"bulk{n}", shape=(n, n, n), periodic=(True, True, True),
+                L1=2.32, L2=0.0, L3=0.0, objects=[], dir_seed=seed, prec=prec,
+                fire=dict(FIRE, force_tol=1e-9, max_steps=2000))
+
+
 def colloid_slab(n=128, seed=1, with_colloid=True):
     """n^3 box: object planes z = 0 and z = n-1 with x-aligned Nobili-Durand
     anchoring W = 0.5, one sphere of radius 12 at the box centre with
