@@ -48,6 +48,8 @@ def workload(name):
         return synth.bulk32()
     if name == "bulk256":
         return synth.bulk(256)
+    if name == "bulk256_f64":
+        return synth.bulk(256, prec="f64")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -190,6 +192,46 @@ def cpu_leg(cfg):
                        f"2^3 difference choices, gcc -O2, OpenMP over z-planes)")
 
 
+def oracle_steps(name, steps):
+    """Times `steps` whole FIRE steps of the FP64 oracle on workload `name`
+    after an untimed initialisation, with the threads OpenMP gives it."""
+    import oracle
+    from paper_1911_07045_amd import synth
+
+    cfg = workload(name)
+    p = oracle.Problem(cfg["shape"], cfg["periodic"], L1=cfg["L1"], L2=cfg["L2"], L3=cfg["L3"],
+                       objects=cfg["objects"])
+    q0 = p.uniaxial(synth.random_directors(cfg["dir_seed"], p.N))
+    prm = oracle.fire_params(force_tol=0.0, max_steps=1 << 40)
+    st, q, v, F = p.fire_init(prm, q0)
+    t0 = time.perf_counter()
+    p.fire_steps(prm, st, q, v, F, steps)
+    dt = time.perf_counter() - t0
+    return {"workload": name, "threads": oracle.threads(), "steps": steps, "seconds": dt,
+            "site_updates_per_s": p.N * steps / dt}
+
+
+def oracle_timing(plan=(("bulk32", 50, 10), ("colloid_slab128", 3, 0), ("multi_colloid256", 2, 0))):
+    """The oracle's FIRE step rate on the small, medium and headline
+    workloads, on all host cores and on one core (each in a child process,
+    since OpenMP fixes its thread count at start-up)."""
+    import subprocess
+
+    rows = []
+    for name, steps_all, steps_one in plan:
+        for threads, steps in ((None, steps_all), (1, steps_one)):
+            if steps <= 0:
+                continue
+            env = dict(os.environ)
+            if threads:
+                env["OMP_NUM_THREADS"] = str(threads)
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-child", name, str(steps)],
+                               env=env, capture_output=True, text=True, check=True)
+            rows.append(json.loads(r.stdout.strip().splitlines()[-1]))
+            print(f"[bench] oracle {rows[-1]}", file=sys.stderr, flush=True)
+    return rows
+
+
 def precision_leg(cfg, steps=2000, polish=200):
     """FP32 state with FP64 reductions for `steps` FIRE steps, then an FP64
     polish of `polish` steps from the FP32 state, against an FP64 run of
@@ -317,6 +359,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--no-minimizers", action="store_true",
                     help="skip the gradient-descent / Nesterov step timings")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the FP64 oracle on several workloads, all cores and one core")
+    ap.add_argument("--oracle-child", nargs=2, metavar=("WORKLOAD", "STEPS"), help=argparse.SUPPRESS)
     ap.add_argument("--kernel-hash", action="store_true",
                     help="print the hash of the kernel sources that a counter summary records")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -324,6 +369,20 @@ def main():
     args = ap.parse_args()
     if args.kernel_hash:
         print(kernel_source_hash())
+        return
+    if args.oracle_child:
+        print(json.dumps(oracle_steps(args.oracle_child[0], int(args.oracle_child[1]))), flush=True)
+        return
+    if args.oracle_timing:
+        import platform
+        cpu = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        except OSError:
+            pass
+        print(json.dumps({"oracle_timing": oracle_timing(), "cpu": cpu, "nproc": os.cpu_count(),
+                          "host": platform.node()}), flush=True)
         return
     if args.copy_calibration:
         copy_calibration()

@@ -138,7 +138,7 @@ static int check_dev_ptr(lq_lattice* lat, const void* ptr, const char* name) {
 // Planes per block: the longest march (at most 64 planes, so the two halo
 // planes cost at most 1/32 of the traffic) that still gives every compute
 // unit its full complement of resident blocks.
-static int pick_zc(const lq_params& p, int device, bool l23) {
+static int pick_zc(const lq_params& p, int device, bool l23, int wide) {
     const char* env = std::getenv("LQ_ZC");
     if (env) {
         int z = std::atoi(env);
@@ -147,17 +147,17 @@ static int pick_zc(const lq_params& p, int device, bool l23) {
     int n_cu = 0;
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n_cu <= 0)
         n_cu = 256;
-    const int64_t resident = (int64_t)n_cu * step_blocks_per_cu(p.prec, l23);
-    const int tx = tile_x(p.prec), ty = tile_y(p.prec);
+    const int64_t resident = (int64_t)n_cu * step_blocks_per_cu(p.prec, l23, wide);
+    const int tx = tile_x(p.prec, l23, wide), ty = tile_y(p.prec, l23, wide);
     const int64_t ntx = (p.n[0] + tx - 1) / tx, nty = (p.n[1] + ty - 1) / ty;
     int zc = 64;
     while (zc > 4 && ntx * nty * ((p.n[2] + zc - 1) / zc) < resident) zc /= 2;
     return zc;
 }
 
-static void tile_flags(const lq_params& p, const std::vector<uint8_t>& mask, int zc, int ntx, int nty,
-                       int ntz, std::vector<uint8_t>& out) {
-    const int64_t TX = tile_x(p.prec), TY = tile_y(p.prec);
+static void tile_flags(const lq_params& p, bool l23, int wide, const std::vector<uint8_t>& mask, int zc,
+                       int ntx, int nty, int ntz, std::vector<uint8_t>& out) {
+    const int64_t TX = tile_x(p.prec, l23, wide), TY = tile_y(p.prec, l23, wide);
     const int64_t nx = p.n[0], ny = p.n[1], nz = p.n[2];
     out.assign((size_t)ntx * nty * ntz, 0);
     auto wrap = [](int64_t g, int64_t n, bool per) -> int64_t {
@@ -208,12 +208,14 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     for (int k = 0; k < 3; ++k) d.per[k] = p.periodic[k];
     d.N = lat->N;
     d.A = p.A; d.B = p.B; d.C = p.C; d.L1 = p.L1; d.L2 = p.L2; d.L3 = p.L3; d.L4 = p.L4;
-    d.zc = pick_zc(p, lat->device, lat->l23);
-    d.ntx = (int)((p.n[0] + tile_x(p.prec) - 1) / tile_x(p.prec));
-    d.nty = (int)((p.n[1] + tile_y(p.prec) - 1) / tile_y(p.prec));
+    d.wide = tile_wide_for(p.n[0], p.prec, lat->l23);
+    d.zc = pick_zc(p, lat->device, lat->l23, d.wide);
+    const int tx = tile_x(p.prec, lat->l23, d.wide), ty = tile_y(p.prec, lat->l23, d.wide);
+    d.ntx = (int)((p.n[0] + tx - 1) / tx);
+    d.nty = (int)((p.n[1] + ty - 1) / ty);
     d.ntz = (int)((p.n[2] + d.zc - 1) / d.zc);
     std::vector<uint8_t> tiles;
-    tile_flags(p, g.mask, d.zc, d.ntx, d.nty, d.ntz, tiles);
+    tile_flags(p, lat->l23, d.wide, g.mask, d.zc, d.ntx, d.nty, d.ntz, tiles);
     HIPCHK(lat, hipMalloc(&lat->d_mask, (size_t)lat->N));
     HIPCHK(lat, hipMemcpy(lat->d_mask, g.mask.data(), (size_t)lat->N, hipMemcpyHostToDevice));
     HIPCHK(lat, hipMalloc(&lat->d_tile, tiles.size()));
@@ -660,13 +662,13 @@ struct lq_batch {
     int prec = -1;
     bool l23 = false;
     MemberDev* d_mem = nullptr;
-    int* d_tile_off = nullptr;
+    int* d_tile_off = nullptr;   // narrow group's offsets, then the wide group's
     int* d_fin_off = nullptr;
     FireDev* d_gather = nullptr;
-    MemberDev* h_mem = nullptr;  // pinned
-    int* h_off = nullptr;        // pinned: tile offsets then finalize offsets
-    FireDev* h_gather = nullptr; // pinned
-    int total_tiles = 0, total_fin = 0;
+    MemberDev* h_mem = nullptr;  // pinned, device order: narrow-tile members first
+    int* h_off = nullptr;        // pinned: tile offsets (capacity + 2), then finalize offsets (capacity + 1)
+    FireDev* h_gather = nullptr; // pinned, device order
+    std::vector<int> order;      // device order -> index in members
 };
 
 static int fin_blocks_of(const lq_lattice* lat) {
@@ -686,11 +688,11 @@ int lq_batch_create(int32_t capacity, void* stream, lq_batch** out) {
     b->stream = (hipStream_t)stream;
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) e = hipMalloc(&b->d_mem, sizeof(MemberDev) * capacity);
-    if (e == hipSuccess) e = hipMalloc(&b->d_tile_off, sizeof(int) * (capacity + 1));
+    if (e == hipSuccess) e = hipMalloc(&b->d_tile_off, sizeof(int) * (capacity + 2));
     if (e == hipSuccess) e = hipMalloc(&b->d_fin_off, sizeof(int) * (capacity + 1));
     if (e == hipSuccess) e = hipMalloc(&b->d_gather, sizeof(FireDev) * capacity);
     if (e == hipSuccess) e = hipHostMalloc(&b->h_mem, sizeof(MemberDev) * capacity, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc(&b->h_off, sizeof(int) * 2 * (capacity + 1), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_off, sizeof(int) * (2 * capacity + 3), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&b->h_gather, sizeof(FireDev) * capacity, hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -758,48 +760,58 @@ int lq_batch_step(lq_batch* b, int64_t n_steps, lq_fire_report* reports) {
     for (lq_lattice* m : b->members)
         if (!m->bound) return fail(nullptr, LQ_ESTATE, "a member lost its FIRE binding; remove it or bind it again");
     // the descriptors are rebuilt on every call (a few hundred bytes per
-    // member), so members re-bound by lq_fire_init are picked up
-    {
-        int t = 0, f = 0;
-        for (int i = 0; i < n; ++i) {
-            lq_lattice* m = b->members[i];
-            MemberDev& d = b->h_mem[i];
-            std::memset(&d, 0, sizeof(d));
-            d.L = m->dev;
-            const Bufs<double>& bb = m->b64;
-            for (int k = 0; k < 2; ++k) {
-                d.q[k] = bb.q[k];
-                d.v[k] = bb.v[k];
-                d.F[k] = bb.F[k];
-            }
-            d.partials = m->d_partials;
-            d.st = m->d_state;
-            d.nblocks = (int)n_step_blocks(m->dev);
-            b->h_off[i] = t;
-            b->h_off[(b->capacity + 1) + i] = f;
-            t += d.nblocks;
-            f += fin_blocks_of(m);
+    // member), so members re-bound by lq_fire_init are picked up.  Members
+    // on narrow tiles come first and run in one launch per step, members on
+    // wide tiles in a second one.
+    b->order.clear();
+    for (int w = 0; w < 2; ++w)
+        for (int i = 0; i < n; ++i)
+            if (b->members[i]->dev.wide == w) b->order.push_back(i);
+    int n_narrow = 0;
+    while (n_narrow < n && !b->members[b->order[n_narrow]]->dev.wide) ++n_narrow;
+    const int n_wide = n - n_narrow;
+    int* tile_off = b->h_off;                     // narrow: [0, n_narrow], wide: [n_narrow + 1, n + 1]
+    int* fin_off = b->h_off + (b->capacity + 2);  // [0, n]
+    int tiles[2] = {0, 0}, f = 0;
+    for (int j = 0; j < n; ++j) {
+        lq_lattice* m = b->members[b->order[j]];
+        const int grp = j < n_narrow ? 0 : 1;
+        MemberDev& d = b->h_mem[j];
+        std::memset(&d, 0, sizeof(d));
+        d.L = m->dev;
+        const Bufs<double>& bb = m->b64;
+        for (int k = 0; k < 2; ++k) {
+            d.q[k] = bb.q[k];
+            d.v[k] = bb.v[k];
+            d.F[k] = bb.F[k];
         }
-        b->h_off[n] = t;
-        b->h_off[(b->capacity + 1) + n] = f;
-        b->total_tiles = t;
-        b->total_fin = f;
-        HIPCHK(nullptr, hipMemcpyAsync(b->d_mem, b->h_mem, sizeof(MemberDev) * n, hipMemcpyHostToDevice, b->stream));
-        HIPCHK(nullptr, hipMemcpyAsync(b->d_tile_off, b->h_off, sizeof(int) * (n + 1), hipMemcpyHostToDevice,
-                                       b->stream));
-        HIPCHK(nullptr, hipMemcpyAsync(b->d_fin_off, b->h_off + (b->capacity + 1), sizeof(int) * (n + 1),
-                                       hipMemcpyHostToDevice, b->stream));
+        d.partials = m->d_partials;
+        d.st = m->d_state;
+        d.nblocks = (int)n_step_blocks(m->dev);
+        tile_off[grp == 0 ? j : j + 1] = tiles[grp];
+        fin_off[j] = f;
+        tiles[grp] += d.nblocks;
+        f += fin_blocks_of(m);
     }
-    int rc = launch_batch_steps(b->prec, b->l23, b->d_mem, b->d_tile_off, n, b->total_tiles, b->d_fin_off,
-                                b->total_fin, b->d_gather, n_steps, b->stream);
+    tile_off[n_narrow] = tiles[0];
+    tile_off[n + 1] = tiles[1];
+    fin_off[n] = f;
+    HIPCHK(nullptr, hipMemcpyAsync(b->d_mem, b->h_mem, sizeof(MemberDev) * n, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(nullptr, hipMemcpyAsync(b->d_tile_off, tile_off, sizeof(int) * (n + 2), hipMemcpyHostToDevice,
+                                   b->stream));
+    HIPCHK(nullptr, hipMemcpyAsync(b->d_fin_off, fin_off, sizeof(int) * (n + 1), hipMemcpyHostToDevice, b->stream));
+    int rc = launch_batch_steps(b->prec, b->l23, b->d_mem, n_narrow, b->d_tile_off, tiles[0], n_wide,
+                                b->d_tile_off + n_narrow + 1, tiles[1], b->d_fin_off, f, b->d_gather, n_steps,
+                                b->stream);
     if (rc != LQ_OK) return fail(nullptr, rc, "batch kernel launch failed");
     HIPCHK(nullptr, hipMemcpyAsync(b->h_gather, b->d_gather, sizeof(FireDev) * n, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(nullptr, hipStreamSynchronize(b->stream));
     int worst = LQ_OK;
-    for (int i = 0; i < n; ++i) {
-        fill_report(b->h_gather[i], &reports[i]);
-        *b->members[i]->h_state = b->h_gather[i];
-        if (b->h_gather[i].status == LQ_NONFINITE) worst = LQ_ENONFINITE;
+    for (int j = 0; j < n; ++j) {
+        const int i = b->order[j];
+        fill_report(b->h_gather[j], &reports[i]);
+        *b->members[i]->h_state = b->h_gather[j];
+        if (b->h_gather[j].status == LQ_NONFINITE) worst = LQ_ENONFINITE;
     }
     if (worst != LQ_OK) return fail(nullptr, worst, "a member's FIRE reduction is not finite");
     return LQ_OK;

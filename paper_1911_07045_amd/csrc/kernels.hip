@@ -252,10 +252,10 @@ __device__ __forceinline__ void chiral_nb(int k, const T qx[5], T h[5]) {
 // the centre, read from the LDS slots of the planes below, at and above the
 // centre.  BULK: every site of the padded tile is simulated with all six
 // neighbours, so masks are compile-time constants.
-template <typename T, bool L23, bool BULK>
+template <typename T, bool L23, bool BULK, int W>
 struct Stencil {
-    T (*q)[5][Tile<T>::PY][Tile<T>::PX];
-    uint8_t (*m)[Tile<T>::PY][Tile<T>::PX];
+    T (*q)[5][Tile<T, L23, W>::PY][Tile<T, L23, W>::PX];
+    uint8_t (*m)[Tile<T, L23, W>::PY][Tile<T, L23, W>::PX];
     int s[3];  // LDS slots of the planes below, at and above the centre
     int cx, cy;
     __device__ __forceinline__ T at(int dx, int dy, int dz, int c) const {
@@ -278,8 +278,8 @@ __device__ __forceinline__ void unit(int k, int s, int& dx, int& dy, int& dz) {
 }
 
 // mean differences C_k (k != skip) at offset o of the stencil
-template <typename T, bool L23, bool BULK>
-__device__ __forceinline__ void mean_diffs(const Stencil<T, L23, BULK>& P, int ox, int oy, int oz,
+template <typename T, bool L23, bool BULK, int W>
+__device__ __forceinline__ void mean_diffs(const Stencil<T, L23, BULK, W>& P, int ox, int oy, int oz,
                                            int skip, uint32_t m, T Ck[3][5]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -303,8 +303,8 @@ __device__ __forceinline__ void mean_diffs(const Stencil<T, L23, BULK>& P, int o
 }
 
 // -dE/dq at the stencil centre (a simulated site with mask m0).
-template <typename T, bool L23, bool BULK>
-__device__ __forceinline__ void site_force(const Stencil<T, L23, BULK>& P, uint32_t m0,
+template <typename T, bool L23, bool BULK, int W>
+__device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, uint32_t m0,
                                            const LatDev& L, int site, T F[5]) {
     const T A = T(L.A), B = T(L.B), C = T(L.C), L1 = T(L.L1);
     T q0[5];
@@ -577,25 +577,26 @@ __device__ void grid_finish(double r[4], double* partials, FireDev* st, int nblo
 // (steering, first half kick, q += dt v) into an LDS slot.  Loads run one
 // plane ahead of the drift, so the loads of plane i+1 are in flight while the
 // force of plane i-1 is evaluated.
-template <typename T>
+template <typename T, bool L23, int W>
 __device__ __forceinline__ void ring_pos(int r, int& px, int& py) {
-    constexpr int PX = Tile<T>::PX, PY = Tile<T>::PY;
+    constexpr int PX = Tile<T, L23, W>::PX, PY = Tile<T, L23, W>::PY;
     if (r < PX) { px = r; py = 0; }
     else if (r < 2 * PX) { px = r - PX; py = PY - 1; }
     else if (r < 2 * PX + PY - 2) { px = 0; py = r - 2 * PX + 1; }
     else { px = PX - 1; py = r - 2 * PX - (PY - 2) + 1; }
 }
 
-template <typename T, bool L23, int MODE, bool BULK>
+template <typename T, bool L23, int MODE, bool BULK, int W>
 __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_in,
                                       const T* __restrict__ v_in, const T* __restrict__ F_in,
                                       T* __restrict__ q_out, T* __restrict__ v_out,
                                       T* __restrict__ F_out, T cv, T cF, T dt, T hdt, int x0, int y0,
-                                      int z0, int zc, T (*sq)[5][Tile<T>::PY][Tile<T>::PX],
-                                      uint8_t (*sm)[Tile<T>::PY][Tile<T>::PX], double red[4]) {
+                                      int z0, int zc, T (*sq)[5][Tile<T, L23, W>::PY][Tile<T, L23, W>::PX],
+                                      uint8_t (*sm)[Tile<T, L23, W>::PY][Tile<T, L23, W>::PX], double red[4]) {
+    using G = Tile<T, L23, W>;
     constexpr int NS = 4;
-    constexpr int TX = Tile<T>::X, NTHREADS = Tile<T>::N, RING = Tile<T>::RING;
-    constexpr int RING_ITEMS = Tile<T>::RING_ITEMS, ITEMS_PER_THREAD = Tile<T>::IPT;
+    constexpr int TX = G::X, NTHREADS = G::N, RING = G::RING;
+    constexpr int RING_ITEMS = G::RING_ITEMS, ITEMS_PER_THREAD = G::IPT;
     constexpr bool STEP = MODE != MODE_FORCE;
     constexpr bool USES_V = MODE == MODE_FIRE || MODE == MODE_NAG;
     const int64_t N = L.N;
@@ -616,7 +617,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
         it_c[j] = -1; it_px[j] = 0; it_py[j] = 0; it_sxy[j] = -1;
         if (k < RING_ITEMS) {
             it_c[j] = k / RING;
-            ring_pos<T>(k % RING, it_px[j], it_py[j]);
+            ring_pos<T, L23, W>(k % RING, it_px[j], it_py[j]);
             const int wx = wrapc(x0 - 1 + it_px[j], L.nx, L.per[0]);
             const int wy = wrapc(y0 - 1 + it_py[j], L.ny, L.per[1]);
             it_sxy[j] = (wx >= 0 && wy >= 0) ? wx + L.nx * wy : -1;
@@ -749,12 +750,12 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
             const int s = gx + L.nx * gy + nxy * (z0 + f - 1);
             const uint32_t off = (own_xy && in_chunk) ? (uint32_t)s * (uint32_t)sizeof(T) : NONE;
             const bool live = own_xy && in_chunk && (m_older & M_SIM);
-            Stencil<T, L23, BULK> P;
+            Stencil<T, L23, BULK, W> P;
             P.q = sq; P.m = sm;
             P.s[0] = slot_of(f - 1); P.s[1] = slot_of(f); P.s[2] = slot_of(f + 1);
             P.cx = tx + 1; P.cy = ty + 1;
             T F[5];
-            site_force<T, L23, BULK>(P, m_older, L, s, F);
+            site_force<T, L23, BULK, W>(P, m_older, L, s, F);
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 const T Fc = live ? F[c] : T(0);
@@ -787,15 +788,16 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
 // One block of the force / FIRE step: tile `bid` of lattice L.  `nblocks`
 // is the lattice's own tile count; partials are indexed by tile, so the
 // reduction order does not depend on how blocks are dispatched.
-template <typename T, bool L23, int MODE>
+template <typename T, bool L23, int MODE, int W>
 __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, const T* __restrict__ qin,
                                            T* __restrict__ Fout, double* partials, FireDev* st,
                                            int nblocks, int bid) {
     constexpr int NS = 4;
-    constexpr int TX = Tile<T>::X, TY = Tile<T>::Y, PX = Tile<T>::PX, PY = Tile<T>::PY;
+    using G = Tile<T, L23, W>;
+    constexpr int TX = G::X, TY = G::Y, PX = G::PX, PY = G::PY;
     __shared__ T sq[NS][5][PY][PX];
     __shared__ uint8_t sm[NS][PY][PX];
-    __shared__ double scratch[Tile<T>::N / 64][4];
+    __shared__ double scratch[G::N / 64][4];
     __shared__ int last_flag;
 
     const int bx = bid % L.ntx, by = (bid / L.ntx) % L.nty, bz = bid / (L.ntx * L.nty);
@@ -822,23 +824,23 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
     }
     double red[4] = {0.0, 0.0, 0.0, 0.0};
     if (L.tile_bulk[bid])
-        march<T, L23, MODE, true>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
+        march<T, L23, MODE, true, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
                                   sq, sm, red);
     else
-        march<T, L23, MODE, false>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
+        march<T, L23, MODE, false, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
                                    sq, sm, red);
     if (STEP) grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
 }
 
-template <typename T, bool L23, int MODE>
-__global__ __launch_bounds__(Tile<T>::N) __attribute__((amdgpu_waves_per_eu(L23 ? 1 : Tile<T>::WAVES))) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
+template <typename T, bool L23, int MODE, int W>
+__global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_per_eu(Tile<T, L23, W>::WAVES))) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
                                                     T* __restrict__ Fout, double* partials,
                                                     FireDev* st) {
     const int nblocks = (int)gridDim.x;
     int bid = (int)blockIdx.x;
     // keep neighbouring tiles on one XCD: dispatch is round-robin over 8 XCDs
     if ((nblocks & 7) == 0) bid = (bid & 7) * (nblocks >> 3) + (bid >> 3);
-    step_block<T, L23, MODE>(L, b, qin, Fout, partials, st, nblocks, bid);
+    step_block<T, L23, MODE, W>(L, b, qin, Fout, partials, st, nblocks, bid);
 }
 
 // ---------------------------------------------------------------------------
@@ -855,8 +857,8 @@ __device__ __forceinline__ int member_of(const int* __restrict__ off, int n, int
     return lo;
 }
 
-template <typename T, bool L23>
-__global__ __launch_bounds__(Tile<T>::N) __attribute__((amdgpu_waves_per_eu(L23 ? 1 : Tile<T>::WAVES))) void k_march_batch(const MemberDev* __restrict__ mem,
+template <typename T, bool L23, int W>
+__global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_per_eu(Tile<T, L23, W>::WAVES))) void k_march_batch(const MemberDev* __restrict__ mem,
                                                           const int* __restrict__ off, int n_members) {
     const int m = member_of(off, n_members, (int)blockIdx.x);
     const MemberDev& M = mem[m];
@@ -866,7 +868,7 @@ __global__ __launch_bounds__(Tile<T>::N) __attribute__((amdgpu_waves_per_eu(L23 
         b.q[i] = (T*)M.q[i]; b.v[i] = (T*)M.v[i]; b.F[i] = (T*)M.F[i];
     }
     const LatDev& L = M.L;
-    step_block<T, L23, MODE_FIRE>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
+    step_block<T, L23, MODE_FIRE, W>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
                              (int)blockIdx.x - off[m]);
 }
 
@@ -1236,17 +1238,21 @@ static int hip_status(hipError_t e) { return e == hipSuccess ? LQ_OK : LQ_EHIP; 
 int64_t n_step_blocks(const LatDev& L) { return (int64_t)L.ntx * L.nty * L.ntz; }
 
 // Resident blocks per compute unit of the fused FIRE step kernel.
-int step_blocks_per_cu(int prec, bool l23) {
+template <typename T, bool L23, int W>
+static int blocks_per_cu() {
     int n = 0;
-    hipError_t e;
-    if (prec == LQ_F64)
-        e = l23 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<double, true, MODE_FIRE>, Tile<double>::N, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<double, false, MODE_FIRE>, Tile<double>::N, 0);
-    else
-        e = l23 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<float, true, MODE_FIRE>, Tile<float>::N, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<float, false, MODE_FIRE>, Tile<float>::N, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<T, L23, MODE_FIRE, W>, Tile<T, L23, W>::N, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
+int step_blocks_per_cu(int prec, bool l23, int wide) {
+    if (prec == LQ_F64) {
+        if (l23) return wide ? blocks_per_cu<double, true, 1>() : blocks_per_cu<double, true, 0>();
+        return wide ? blocks_per_cu<double, false, 1>() : blocks_per_cu<double, false, 0>();
+    }
+    if (l23) return wide ? blocks_per_cu<float, true, 1>() : blocks_per_cu<float, true, 0>();
+    return wide ? blocks_per_cu<float, false, 1>() : blocks_per_cu<float, false, 0>();
+}
+
 int64_t n_energy_blocks(const LatDev& L) {
     int64_t b = (L.N + 255) / 256;
     return b < 2048 ? b : 2048;
@@ -1257,43 +1263,46 @@ static int grid_1d(int64_t n) {
     return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
 }
 
+template <typename T, int MODE, int W>
+static void launch_march(const LatDev& L, bool l23, const Bufs<T>& b, const void* q, void* F, double* partials,
+                         FireDev* st, hipStream_t s) {
+    const dim3 g((unsigned)n_step_blocks(L));
+    if (l23)
+        k_march<T, true, MODE, W><<<g, Tile<T, true, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st);
+    else
+        k_march<T, false, MODE, W><<<g, Tile<T, false, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st);
+}
+
+template <typename T, int MODE>
+static void launch_march_any(const LatDev& L, bool l23, const Bufs<T>& b, const void* q, void* F, double* partials,
+                             FireDev* st, hipStream_t s) {
+    if (L.wide) launch_march<T, MODE, 1>(L, l23, b, q, F, partials, st, s);
+    else launch_march<T, MODE, 0>(L, l23, b, q, F, partials, st, s);
+}
+
 int launch_forces(const LatDev& L, bool l23, int prec, const void* q, void* F, void* stream) {
-    dim3 g((unsigned)n_step_blocks(L)), blk(prec == LQ_F64 ? Tile<double>::N : Tile<float>::N);
     hipStream_t s = (hipStream_t)stream;
-    if (prec == LQ_F64) {
-        Bufs<double> b{};
-        if (l23) k_march<double, true, MODE_FORCE><<<g, blk, 0, s>>>(L, b, (const double*)q, (double*)F, nullptr, nullptr);
-        else k_march<double, false, MODE_FORCE><<<g, blk, 0, s>>>(L, b, (const double*)q, (double*)F, nullptr, nullptr);
-    } else {
-        Bufs<float> b{};
-        if (l23) k_march<float, true, MODE_FORCE><<<g, blk, 0, s>>>(L, b, (const float*)q, (float*)F, nullptr, nullptr);
-        else k_march<float, false, MODE_FORCE><<<g, blk, 0, s>>>(L, b, (const float*)q, (float*)F, nullptr, nullptr);
-    }
+    if (prec == LQ_F64) launch_march_any<double, MODE_FORCE>(L, l23, Bufs<double>{}, q, F, nullptr, nullptr, s);
+    else launch_march_any<float, MODE_FORCE>(L, l23, Bufs<float>{}, q, F, nullptr, nullptr, s);
     return hip_status(hipGetLastError());
 }
 
 template <int MODE>
 static void launch_step(const LatDev& L, bool l23, int prec, const void* bufs, double* partials, FireDev* st,
-                        dim3 g, dim3 blk, hipStream_t s) {
-    if (prec == LQ_F64) {
-        const Bufs<double>& b = *(const Bufs<double>*)bufs;
-        if (l23) k_march<double, true, MODE><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
-        else k_march<double, false, MODE><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
-    } else {
-        const Bufs<float>& b = *(const Bufs<float>*)bufs;
-        if (l23) k_march<float, true, MODE><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
-        else k_march<float, false, MODE><<<g, blk, 0, s>>>(L, b, nullptr, nullptr, partials, st);
-    }
+                        hipStream_t s) {
+    if (prec == LQ_F64)
+        launch_march_any<double, MODE>(L, l23, *(const Bufs<double>*)bufs, nullptr, nullptr, partials, st, s);
+    else
+        launch_march_any<float, MODE>(L, l23, *(const Bufs<float>*)bufs, nullptr, nullptr, partials, st, s);
 }
 
 int launch_fire_steps(const LatDev& L, bool l23, int prec, int method, const void* bufs, double* partials,
                       FireDev* st, int64_t n_steps, void* stream) {
-    dim3 g((unsigned)n_step_blocks(L)), blk(prec == LQ_F64 ? Tile<double>::N : Tile<float>::N);
     hipStream_t s = (hipStream_t)stream;
     for (int64_t i = 0; i < n_steps; ++i) {
-        if (method == LQ_METHOD_GD) launch_step<MODE_GD>(L, l23, prec, bufs, partials, st, g, blk, s);
-        else if (method == LQ_METHOD_NESTEROV) launch_step<MODE_NAG>(L, l23, prec, bufs, partials, st, g, blk, s);
-        else launch_step<MODE_FIRE>(L, l23, prec, bufs, partials, st, g, blk, s);
+        if (method == LQ_METHOD_GD) launch_step<MODE_GD>(L, l23, prec, bufs, partials, st, s);
+        else if (method == LQ_METHOD_NESTEROV) launch_step<MODE_NAG>(L, l23, prec, bufs, partials, st, s);
+        else launch_step<MODE_FIRE>(L, l23, prec, bufs, partials, st, s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return LQ_EHIP;
     }
@@ -1372,20 +1381,28 @@ int launch_uniaxial(const LatDev& L, int prec, const double* dirs, double S, voi
     return hip_status(hipGetLastError());
 }
 
-int launch_batch_steps(int prec, bool l23, const MemberDev* mem, const int* tile_off, int n_members,
-                       int total_tiles, const int* fin_off, int total_fin, FireDev* gather, int64_t n_steps,
-                       void* stream) {
+template <typename T, int W>
+static void launch_batch_group(bool l23, const MemberDev* mem, const int* off, int n, int tiles, hipStream_t s) {
+    if (n <= 0) return;
+    if (l23) k_march_batch<T, true, W><<<tiles, Tile<T, true, W>::N, 0, s>>>(mem, off, n);
+    else k_march_batch<T, false, W><<<tiles, Tile<T, false, W>::N, 0, s>>>(mem, off, n);
+}
+
+int launch_batch_steps(int prec, bool l23, const MemberDev* mem, int n_narrow, const int* tile_off,
+                       int tiles_narrow, int n_wide, const int* tile_off_wide, int tiles_wide,
+                       const int* fin_off, int total_fin, FireDev* gather, int64_t n_steps, void* stream) {
     hipStream_t s = (hipStream_t)stream;
+    const int n_members = n_narrow + n_wide;
     const int nb = (n_members + 63) / 64;
     k_batch_begin<<<nb, 64, 0, s>>>(mem, n_members, n_steps);
     if (hipGetLastError() != hipSuccess) return LQ_EHIP;
     for (int64_t i = 0; i < n_steps; ++i) {
         if (prec == LQ_F64) {
-            if (l23) k_march_batch<double, true><<<total_tiles, Tile<double>::N, 0, s>>>(mem, tile_off, n_members);
-            else k_march_batch<double, false><<<total_tiles, Tile<double>::N, 0, s>>>(mem, tile_off, n_members);
+            launch_batch_group<double, 0>(l23, mem, tile_off, n_narrow, tiles_narrow, s);
+            launch_batch_group<double, 1>(l23, mem + n_narrow, tile_off_wide, n_wide, tiles_wide, s);
         } else {
-            if (l23) k_march_batch<float, true><<<total_tiles, Tile<float>::N, 0, s>>>(mem, tile_off, n_members);
-            else k_march_batch<float, false><<<total_tiles, Tile<float>::N, 0, s>>>(mem, tile_off, n_members);
+            launch_batch_group<float, 0>(l23, mem, tile_off, n_narrow, tiles_narrow, s);
+            launch_batch_group<float, 1>(l23, mem + n_narrow, tile_off_wide, n_wide, tiles_wide, s);
         }
         if (hipGetLastError() != hipSuccess) return LQ_EHIP;
     }

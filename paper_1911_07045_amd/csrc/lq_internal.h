@@ -36,15 +36,27 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
               const lq_site_anchor* recs, int64_t n_recs, const int64_t* object_sites,
               int64_t n_object_sites, Geometry& g, std::string& err);
 
-// Tile geometry of the fused kernel, per element type: a block of X x Y
-// threads owns an X x Y column tile and marches zc planes along z.  Wider
-// rows give longer contiguous runs per wave; the FP64 tile is narrower so
-// that two blocks still fit the LDS of a compute unit.
+// Tile geometry of the fused kernel, per element type, term set and width
+// kind: a block of X x Y threads owns an X x Y column tile and marches zc
+// planes along z.  Long rows cut the halo's share of the traffic (the two
+// x-edge columns of the ring cost one cache line per row for one value
+// each), so the wide tile is as wide as the block's register budget allows:
+// 1024 threads for the one-constant FP32 kernel (at most 128 VGPRs, four
+// waves per SIMD), 512 for FP32 with L2/L3/L4, 256 for FP64.  Lattices
+// narrower than a wide tile (the small boxes of a serving batch) use the
+// narrow 32 x 8 tile instead, which leaves fewer threads idle.  WAVES is the
+// number of waves per SIMD a kernel is held to (1: no constraint).
 #ifndef LQ_TILE_X_F32
-#define LQ_TILE_X_F32 64
+#define LQ_TILE_X_F32 128
 #endif
 #ifndef LQ_TILE_Y_F32
 #define LQ_TILE_Y_F32 8
+#endif
+#ifndef LQ_TILE_X_F32_L23
+#define LQ_TILE_X_F32_L23 64
+#endif
+#ifndef LQ_TILE_Y_F32_L23
+#define LQ_TILE_Y_F32_L23 8
 #endif
 #ifndef LQ_TILE_X_F64
 #define LQ_TILE_X_F64 32
@@ -52,7 +64,13 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
 #ifndef LQ_TILE_Y_F64
 #define LQ_TILE_Y_F64 8
 #endif
-template <int TX_, int TY_>
+#ifndef LQ_TILE_X_F64_L23
+#define LQ_TILE_X_F64_L23 32
+#endif
+#ifndef LQ_TILE_Y_F64_L23
+#define LQ_TILE_Y_F64_L23 8
+#endif
+template <int TX_, int TY_, int WAVES_>
 struct TileGeom {
     static constexpr int X = TX_, Y = TY_;
     static constexpr int N = X * Y;            // threads per block
@@ -60,23 +78,37 @@ struct TileGeom {
     static constexpr int RING = 2 * PX + 2 * (PY - 2);
     static constexpr int RING_ITEMS = 5 * RING;   // (site, component) pairs of the ring
     static constexpr int IPT = (RING_ITEMS + N - 1) / N;
+    static constexpr int WAVES = WAVES_;
 };
-template <typename T>
+// W = 1: wide tile, W = 0: narrow tile
+template <typename T, bool L23, int W>
 struct Tile;
-// WAVES: waves per SIMD the one-constant (L1) step kernels are held to
-// (register budget 512 / WAVES), so that two FP32 blocks share a compute
-// unit; the L2/L3 kernels need more registers than that allows without
-// spilling and are left unconstrained.
 template <>
-struct Tile<float> : TileGeom<LQ_TILE_X_F32, LQ_TILE_Y_F32> {
-    static constexpr int WAVES = 4;
-};
+struct Tile<float, false, 1> : TileGeom<LQ_TILE_X_F32, LQ_TILE_Y_F32, 4> {};
 template <>
-struct Tile<double> : TileGeom<LQ_TILE_X_F64, LQ_TILE_Y_F64> {
-    static constexpr int WAVES = 1;
-};
-inline int tile_x(int prec) { return prec == LQ_F64 ? Tile<double>::X : Tile<float>::X; }
-inline int tile_y(int prec) { return prec == LQ_F64 ? Tile<double>::Y : Tile<float>::Y; }
+struct Tile<float, true, 1> : TileGeom<LQ_TILE_X_F32_L23, LQ_TILE_Y_F32_L23, 1> {};
+template <>
+struct Tile<double, false, 1> : TileGeom<LQ_TILE_X_F64, LQ_TILE_Y_F64, 1> {};
+template <>
+struct Tile<double, true, 1> : TileGeom<LQ_TILE_X_F64_L23, LQ_TILE_Y_F64_L23, 1> {};
+template <typename T, bool L23>
+struct Tile<T, L23, 0> : TileGeom<32, 8, Tile<T, L23, 1>::WAVES> {};
+
+template <int W>
+inline int tile_x_w(int prec, bool l23) {
+    if (prec == LQ_F64) return l23 ? Tile<double, true, W>::X : Tile<double, false, W>::X;
+    return l23 ? Tile<float, true, W>::X : Tile<float, false, W>::X;
+}
+template <int W>
+inline int tile_y_w(int prec, bool l23) {
+    if (prec == LQ_F64) return l23 ? Tile<double, true, W>::Y : Tile<double, false, W>::Y;
+    return l23 ? Tile<float, true, W>::Y : Tile<float, false, W>::Y;
+}
+inline int tile_x(int prec, bool l23, int wide) { return wide ? tile_x_w<1>(prec, l23) : tile_x_w<0>(prec, l23); }
+inline int tile_y(int prec, bool l23, int wide) { return wide ? tile_y_w<1>(prec, l23) : tile_y_w<0>(prec, l23); }
+inline int tile_threads(int prec, bool l23, int wide) { return tile_x(prec, l23, wide) * tile_y(prec, l23, wide); }
+// a lattice narrower than one wide tile takes the narrow one
+inline int tile_wide_for(int64_t nx, int prec, bool l23) { return nx >= tile_x_w<1>(prec, l23) ? 1 : 0; }
 
 // Device view of a lattice.
 struct LatDev {
@@ -91,6 +123,7 @@ struct LatDev {
     double ext[5];              // constant external-field force per simulated site
     double A, B, C, L1, L2, L3, L4;
     int zc, ntx, nty, ntz;
+    int wide;  // tile width kind of the step kernels (1 wide, 0 narrow)
 };
 
 // FIRE state kept in device memory.
@@ -153,11 +186,13 @@ int launch_energy(const LatDev& L, bool l23, int prec, const void* q, double* pa
                   EnergyOut* out, uint32_t* ticket, void* stream);
 int launch_uniaxial(const LatDev& L, int prec, const double* dirs, double S, void* q,
                     void* stream);
-int launch_batch_steps(int prec, bool l23, const MemberDev* mem, const int* tile_off, int n_members,
-                       int total_tiles, const int* fin_off, int total_fin, FireDev* gather, int64_t n_steps,
-                       void* stream);
+// Members [0, n_narrow) of mem use narrow tiles, the next n_wide wide ones;
+// tile_off / tile_off_wide hold each group's cumulative tile offsets.
+int launch_batch_steps(int prec, bool l23, const MemberDev* mem, int n_narrow, const int* tile_off,
+                       int tiles_narrow, int n_wide, const int* tile_off_wide, int tiles_wide,
+                       const int* fin_off, int total_fin, FireDev* gather, int64_t n_steps, void* stream);
 int64_t n_step_blocks(const LatDev& L);
-int step_blocks_per_cu(int prec, bool l23);
+int step_blocks_per_cu(int prec, bool l23, int wide);
 int64_t n_energy_blocks(const LatDev& L);
 
 }  // namespace lq

@@ -124,3 +124,28 @@ def test_server_results_equal_alone_and_budget_holds():
         qs, steps, status = solo[res.id]
         assert res.steps == steps and res.status == status
         assert torch.equal(srv.states[res.id][0], qs)
+
+
+def test_batch_mixing_narrow_and_wide_tiles_equals_alone():
+    """A box narrower than one wide tile runs on narrow tiles, a wide box on
+    wide ones; in one batch the two groups go in separate launches and each
+    member still follows its solo trajectory bit for bit."""
+    say("[batch] narrow + wide members")
+    reqs = _reqs(2, 24, force_tol=0.0, max_steps=10 ** 6)
+    reqs[1]["shape"] = (136, 20, 18)
+    reqs[1]["objects"] = [dict(kind="sphere", center=(60.0, 9.5, 8.5), radius=4.0, law="rp", W=3.0,
+                               dir="normal")]
+    alone = []
+    for r in reqs:
+        lat, q, v, F = _bound(r, "f32")
+        lat.fire_step(37)
+        alone.append((q.cpu(), v.cpu(), F.cpu()))
+        lat.close()
+    b = lqfire.Batch(4)
+    held = [_bound(r, "f32") for r in reqs]
+    for h in held[::-1]:
+        b.add(h[0])
+    b.step(20)
+    b.step(17)
+    for (lat, q, v, F), (qa, va, Fa) in zip(held, alone):
+        assert torch.equal(q.cpu(), qa) and torch.equal(v.cpu(), va) and torch.equal(F.cpu(), Fa)
