@@ -42,7 +42,8 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
 // x-edge columns of the ring cost one cache line per row for one value
 // each), so the wide tile is as wide as the block's register budget allows:
 // 1024 threads for the one-constant FP32 kernel (at most 128 VGPRs, four
-// waves per SIMD), 512 for FP32 with L2/L3/L4, 256 for FP64.  Lattices
+// waves per SIMD), 512 for FP32 with L2/L3/L4 and for one-constant FP64,
+// 256 (64 x 4) for FP64 with L2/L3/L4.  Lattices
 // narrower than a wide tile (the small boxes of a serving batch) use the
 // narrow 32 x 8 tile instead, which leaves fewer threads idle.  WAVES is the
 // number of waves per SIMD a kernel is held to (1: no constraint).
@@ -59,16 +60,16 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
 #define LQ_TILE_Y_F32_L23 8
 #endif
 #ifndef LQ_TILE_X_F64
-#define LQ_TILE_X_F64 32
+#define LQ_TILE_X_F64 64
 #endif
 #ifndef LQ_TILE_Y_F64
 #define LQ_TILE_Y_F64 8
 #endif
 #ifndef LQ_TILE_X_F64_L23
-#define LQ_TILE_X_F64_L23 32
+#define LQ_TILE_X_F64_L23 64
 #endif
 #ifndef LQ_TILE_Y_F64_L23
-#define LQ_TILE_Y_F64_L23 8
+#define LQ_TILE_Y_F64_L23 4
 #endif
 template <int TX_, int TY_, int WAVES_>
 struct TileGeom {
