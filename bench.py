@@ -50,6 +50,10 @@ def workload(name):
         return synth.bulk(256)
     if name == "bulk256_f64":
         return synth.bulk(256, prec="f64")
+    if name == "bulk256_l23":
+        c = synth.bulk(256)
+        c.update(name="bulk256_l23", L2=1.16, L3=1.16)
+        return c
     raise SystemExit(f"unknown workload {name}")
 
 

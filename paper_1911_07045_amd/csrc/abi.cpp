@@ -28,6 +28,7 @@ struct lq_lattice {
     // device geometry
     uint8_t* d_mask = nullptr;
     uint8_t* d_tile = nullptr;
+    uint64_t* d_tile_planes = nullptr;
     int32_t* d_anch_index = nullptr;
     double* d_anch_data = nullptr;
     int n_anch = 0;
@@ -158,44 +159,59 @@ static int pick_zc(const lq_params& p, int device, bool l23, int wide) {
     return zc;
 }
 
+// Per tile: whether every site of the padded tile over the whole march is
+// a full bulk site (mask M_FULL), and per plane of the march whether that
+// holds for the plane and both its z-neighbours.
 static void tile_flags(const lq_params& p, bool l23, int wide, const std::vector<uint8_t>& mask, int zc,
-                       int ntx, int nty, int ntz, std::vector<uint8_t>& out) {
+                       int ntx, int nty, int ntz, std::vector<uint8_t>& out, std::vector<uint64_t>& planes) {
     const int64_t TX = tile_x(p.prec, l23, wide), TY = tile_y(p.prec, l23, wide);
     const int64_t nx = p.n[0], ny = p.n[1], nz = p.n[2];
     out.assign((size_t)ntx * nty * ntz, 0);
+    planes.assign((size_t)ntx * nty * ntz, 0);
     auto wrap = [](int64_t g, int64_t n, bool per) -> int64_t {
         if (g >= 0 && g < n) return g;
         if (!per) return -1;
         g %= n;
         return g < 0 ? g + n : g;
     };
+    std::vector<uint8_t> full;  // per plane z0 - 1 .. z0 + zc of one tile
     for (int bz = 0; bz < ntz; ++bz)
         for (int by = 0; by < nty; ++by)
             for (int bx = 0; bx < ntx; ++bx) {
-                bool ok = true;
                 const int64_t z0 = (int64_t)bz * zc, zc_eff = std::min<int64_t>(zc, nz - z0);
-                for (int64_t z = z0 - 1; ok && z <= z0 + zc_eff; ++z) {
-                    int64_t wz = wrap(z, nz, p.periodic[2]);
-                    if (wz < 0) { ok = false; break; }
+                full.assign((size_t)zc_eff + 2, 0);
+                for (int64_t i = 0; i < zc_eff + 2; ++i) {
+                    const int64_t wz = wrap(z0 - 1 + i, nz, p.periodic[2]);
+                    bool ok = wz >= 0;
                     for (int64_t y = (int64_t)by * TY - 1; ok && y <= (int64_t)by * TY + TY; ++y) {
-                        int64_t wy = wrap(y, ny, p.periodic[1]);
+                        const int64_t wy = wrap(y, ny, p.periodic[1]);
                         if (wy < 0) { ok = false; break; }
                         for (int64_t x = (int64_t)bx * TX - 1; x <= (int64_t)bx * TX + TX; ++x) {
-                            int64_t wx = wrap(x, nx, p.periodic[0]);
+                            const int64_t wx = wrap(x, nx, p.periodic[0]);
                             if (wx < 0 || mask[wx + nx * (wy + ny * wz)] != M_FULL) { ok = false; break; }
                         }
                     }
+                    full[i] = ok ? 1 : 0;
                 }
-                out[bx + (size_t)ntx * (by + (size_t)nty * bz)] = ok ? 1 : 0;
+                bool all = true;
+                uint64_t bits = 0;
+                for (int64_t i = 0; i < zc_eff + 2; ++i) all = all && full[i];
+                for (int64_t f = 0; f < std::min<int64_t>(zc_eff, 64); ++f)
+                    if (full[f] && full[f + 1] && full[f + 2]) bits |= (uint64_t)1 << f;
+                const size_t t = bx + (size_t)ntx * (by + (size_t)nty * bz);
+                out[t] = all ? 1 : 0;
+                planes[t] = bits;
             }
 }
 
 static void free_geometry(lq_lattice* lat) {
     if (lat->d_mask) (void)hipFree(lat->d_mask);
     if (lat->d_tile) (void)hipFree(lat->d_tile);
+    if (lat->d_tile_planes) (void)hipFree(lat->d_tile_planes);
     if (lat->d_anch_index) (void)hipFree(lat->d_anch_index);
     if (lat->d_anch_data) (void)hipFree(lat->d_anch_data);
     lat->d_mask = lat->d_tile = nullptr;
+    lat->d_tile_planes = nullptr;
     lat->d_anch_index = nullptr;
     lat->d_anch_data = nullptr;
 }
@@ -218,11 +234,15 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     d.nty = (int)((p.n[1] + ty - 1) / ty);
     d.ntz = (int)((p.n[2] + d.zc - 1) / d.zc);
     std::vector<uint8_t> tiles;
-    tile_flags(p, lat->l23, d.wide, g.mask, d.zc, d.ntx, d.nty, d.ntz, tiles);
+    std::vector<uint64_t> tile_planes;
+    tile_flags(p, lat->l23, d.wide, g.mask, d.zc, d.ntx, d.nty, d.ntz, tiles, tile_planes);
     HIPCHK(lat, hipMalloc(&lat->d_mask, (size_t)lat->N));
     HIPCHK(lat, hipMemcpy(lat->d_mask, g.mask.data(), (size_t)lat->N, hipMemcpyHostToDevice));
     HIPCHK(lat, hipMalloc(&lat->d_tile, tiles.size()));
     HIPCHK(lat, hipMemcpy(lat->d_tile, tiles.data(), tiles.size(), hipMemcpyHostToDevice));
+    HIPCHK(lat, hipMalloc(&lat->d_tile_planes, tile_planes.size() * sizeof(uint64_t)));
+    HIPCHK(lat, hipMemcpy(lat->d_tile_planes, tile_planes.data(), tile_planes.size() * sizeof(uint64_t),
+                          hipMemcpyHostToDevice));
     lat->n_anch = (int)g.anch_site.size();
     if (lat->n_anch > 0) {
         // dense per-site row index (1-based; 0 = no anchoring)
@@ -236,6 +256,7 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     }
     d.mask = lat->d_mask;
     d.tile_bulk = lat->d_tile;
+    d.tile_planes = lat->d_tile_planes;
     d.n_anch = lat->n_anch;
     d.anch_index = lat->d_anch_index;
     d.anch_data = lat->d_anch_data;

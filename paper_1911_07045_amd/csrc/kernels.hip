@@ -352,7 +352,40 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
                 }
             }
     }
-    if (L23) {
+    if (L23 && BULK) {
+        // cross-axis part in the bulk, where every mean difference is central:
+        // sum over x = centre -+ e_j of +-1/2 h_j(x) collapses to
+        // -1/4 sum_{j<k} (M_jk + M_kj) D_jk, with D_jk the mixed second
+        // difference q(+j+k) - q(+j-k) - q(-j+k) + q(-j-k) and M_jk the map
+        // from C_k to h_j (cross_h with only C_k set)
+        const T L2 = T(L.L2), L3 = T(L.L3);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = j + 1; k < 3; ++k) {
+                int pj[3], pk[3];
+                unit(j, 1, pj[0], pj[1], pj[2]);
+                unit(k, 1, pk[0], pk[1], pk[2]);
+                T C1[3][5], C2[3][5], h1[5], h2[5];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    const T d = (P.at(pj[0] + pk[0], pj[1] + pk[1], pj[2] + pk[2], c) -
+                                 P.at(pj[0] - pk[0], pj[1] - pk[1], pj[2] - pk[2], c)) -
+                                (P.at(pk[0] - pj[0], pk[1] - pj[1], pk[2] - pj[2], c) -
+                                 P.at(-pj[0] - pk[0], -pj[1] - pk[1], -pj[2] - pk[2], c));
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) {
+                        C1[m][c] = m == k ? d : T(0);
+                        C2[m][c] = m == j ? d : T(0);
+                    }
+                }
+                cross_h(j, C1, L2, L3, h1);
+                cross_h(k, C2, L2, L3, h2);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) g[c] = fma_t(T(-0.25), h1[c] + h2[c], g[c]);
+            }
+    }
+    if (L23 && !BULK) {
         const T L2 = T(L.L2), L3 = T(L.L3);
         // cross-axis part: every site x whose mean difference C_j contains Q(centre)
 #pragma unroll
@@ -383,6 +416,8 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
                 for (int c = 0; c < 5; ++c) g[c] = fma_t(a0, h[c], g[c]);
             }
         }
+    }
+    if (L23) {
         if (L.L4 != 0.0) {
             // chiral term: the site's own tensor, then every C_k(x) holding Q(centre)
             const T hL4 = T(0.5 * L.L4);
@@ -592,7 +627,8 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                                       T* __restrict__ q_out, T* __restrict__ v_out,
                                       T* __restrict__ F_out, T cv, T cF, T dt, T hdt, int x0, int y0,
                                       int z0, int zc, T (*sq)[5][Tile<T, L23, W>::PY][Tile<T, L23, W>::PX],
-                                      uint8_t (*sm)[Tile<T, L23, W>::PY][Tile<T, L23, W>::PX], double red[4]) {
+                                      uint8_t (*sm)[Tile<T, L23, W>::PY][Tile<T, L23, W>::PX], double red[4],
+                                      uint64_t plane_bulk) {
     using G = Tile<T, L23, W>;
     constexpr int NS = 4;
     constexpr int TX = G::X, NTHREADS = G::N, RING = G::RING;
@@ -755,7 +791,19 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
             P.s[0] = slot_of(f - 1); P.s[1] = slot_of(f); P.s[2] = slot_of(f + 1);
             P.cx = tx + 1; P.cy = ty + 1;
             T F[5];
-            site_force<T, L23, BULK, W>(P, m_older, L, s, F);
+            // a plane whose 3 x 3 x 3 neighbourhoods are all full bulk sites
+            // takes the bulk evaluation also inside a boundary tile (wide
+            // tiles only: the narrow ones serve small boxes, where few planes
+            // qualify and the extra code costs registers)
+            if (W == 1 && !BULK && f >= 1 && f <= 64 && ((plane_bulk >> (f - 1)) & 1)) {
+                Stencil<T, L23, true, W> PB;
+                PB.q = sq; PB.m = sm;
+                PB.s[0] = P.s[0]; PB.s[1] = P.s[1]; PB.s[2] = P.s[2];
+                PB.cx = P.cx; PB.cy = P.cy;
+                site_force<T, L23, true, W>(PB, (uint32_t)M_FULL, L, s, F);
+            } else {
+                site_force<T, L23, BULK, W>(P, m_older, L, s, F);
+            }
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 const T Fc = live ? F[c] : T(0);
@@ -825,10 +873,10 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
     double red[4] = {0.0, 0.0, 0.0, 0.0};
     if (L.tile_bulk[bid])
         march<T, L23, MODE, true, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
-                                  sq, sm, red);
+                                  sq, sm, red, ~(uint64_t)0);
     else
         march<T, L23, MODE, false, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
-                                   sq, sm, red);
+                                   sq, sm, red, L.tile_planes[bid]);
     if (STEP) grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
 }
 

@@ -118,6 +118,8 @@ struct LatDev {
     int64_t N;
     const uint8_t* mask;
     const uint8_t* tile_bulk;  // 1: every site of the padded tile has mask M_FULL
+    const uint64_t* tile_planes;  // bit i: plane z0 + i of the tile and both its z-neighbours are
+                                  // M_FULL over the padded tile (the first 64 planes of a march)
     int n_anch;
     const int32_t* anch_index;  // per site: 1 + row of anch_data, 0 when not anchored
     const double* anch_data;    // ANCH_STRIDE per anchored site
