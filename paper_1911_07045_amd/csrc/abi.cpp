@@ -138,16 +138,13 @@ static int check_dev_ptr(lq_lattice* lat, const void* ptr, const char* name) {
 // z-chunk per block: as long as possible while the grid keeps >= 2048 blocks
 // Planes per block: the longest march (at most 64 planes, so the two halo
 // planes cost at most 1/32 of the traffic) that still gives every compute
-// unit its full complement of resident blocks.  Lattices on narrow tiles
-// are small boxes that a serving batch runs many at a time; they march 16
-// planes, so the halo planes stay at 1/8 of the traffic.
+// unit its full complement of resident blocks, and at least 4.
 static int pick_zc(const lq_params& p, int device, bool l23, int wide) {
     const char* env = std::getenv("LQ_ZC");
     if (env) {
         int z = std::atoi(env);
         if (z >= 1 && z <= 4096) return z;
     }
-    if (!wide) return 16;
     int n_cu = 0;
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n_cu <= 0)
         n_cu = 256;

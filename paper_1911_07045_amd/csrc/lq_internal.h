@@ -43,10 +43,11 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
 // each), so the wide tile is as wide as the block's register budget allows:
 // 1024 threads for the one-constant FP32 kernel (at most 128 VGPRs, four
 // waves per SIMD), 512 for FP32 with L2/L3/L4 and for one-constant FP64,
-// 256 (64 x 4) for FP64 with L2/L3/L4.  Lattices
-// narrower than a wide tile (the small boxes of a serving batch) use the
-// narrow 32 x 8 tile instead, which leaves fewer threads idle.  WAVES is the
-// number of waves per SIMD a kernel is held to (1: no constraint).
+// 256 (64 x 4) for FP64 with L2/L3/L4.  Lattices narrower than a wide tile
+// (the small boxes of a serving batch) use a narrow tile instead: 64 x 8 in
+// FP32 (on a stream of 16-64-site boxes it gave half the median latency of
+// 32 x 8), 32 x 8 in FP64.  WAVES is the number of waves per SIMD a kernel
+// is held to (1: no constraint).
 #ifndef LQ_TILE_X_F32
 #define LQ_TILE_X_F32 128
 #endif
@@ -92,8 +93,10 @@ template <>
 struct Tile<double, false, 1> : TileGeom<LQ_TILE_X_F64, LQ_TILE_Y_F64, 1> {};
 template <>
 struct Tile<double, true, 1> : TileGeom<LQ_TILE_X_F64_L23, LQ_TILE_Y_F64_L23, 1> {};
-template <typename T, bool L23>
-struct Tile<T, L23, 0> : TileGeom<32, 8, Tile<T, L23, 1>::WAVES> {};
+template <bool L23>
+struct Tile<float, L23, 0> : TileGeom<64, 8, Tile<float, L23, 1>::WAVES> {};
+template <bool L23>
+struct Tile<double, L23, 0> : TileGeom<32, 8, Tile<double, L23, 1>::WAVES> {};
 
 template <int W>
 inline int tile_x_w(int prec, bool l23) {
