@@ -306,12 +306,18 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_07045_amd", "csrc", f) for f in
 
 
 def kernel_source_hash():
+    """sha256 of the kernel sources with comments and whitespace removed, so
+    that only a change of the code itself invalidates a counter summary."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()
 
 

@@ -26,7 +26,11 @@
 // second half kick and writes q, v, F to the other buffer.  Per-block FP64
 // partial sums of F.v, |F|^2, |v|^2 and max|F_i| are combined by the last
 // block to finish (atomic ticket), which then runs the controller.  The host
-// never waits between steps.
+// never waits between steps.  The same march runs gradient descent and
+// Nesterov's accelerated gradient (a compile-time mode) and the force alone.
+// Further kernels: the energy (FP64 per-term sums), the uniaxial initial
+// state, the FIRE bookkeeping, batched steps over many lattices, and the
+// director / defect extraction.
 //
 // Layout: SoA fields [5][nz][ny][nx].  A block owns an X x Y column tile and
 // marches zc planes along z, keeping the drifted q of four planes with their
