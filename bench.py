@@ -357,6 +357,32 @@ def copy_calibration(reps=5):
           flush=True)
 
 
+def copy_ceiling(n=256, fields=15, iters=40):
+    """Streaming ceiling for the step's access pattern: device copies of 15
+    SoA fields of n^3 FP32 values (in -> out), the same 2 x 15 streams a FIRE
+    step reads and writes, timed with HIP events.  Returns TB/s counting read
+    plus written bytes."""
+    import torch
+
+    N = n ** 3
+    src = [torch.zeros(N, dtype=torch.float32, device="cuda") for _ in range(fields)]
+    dst = [torch.empty_like(x) for x in src]
+    for _ in range(3):
+        for a, b in zip(dst, src):
+            a.copy_(b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(iters):
+        for a, b in zip(dst, src):
+            a.copy_(b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    tbs = 2.0 * fields * 4 * N / (ms * 1e-3) / 1e12
+    return {"fields": fields, "sites": N, "ms_per_pass": ms, "TB_per_s": tbs, "frac_hbm_peak": tbs * 1e3 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,6 +398,8 @@ def main():
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only time the FP64 oracle on several workloads, all cores and one core")
     ap.add_argument("--oracle-child", nargs=2, metavar=("WORKLOAD", "STEPS"), help=argparse.SUPPRESS)
+    ap.add_argument("--copy-ceiling", action="store_true",
+                    help="only time plain device copies of the step's 15 fields (streaming ceiling)")
     ap.add_argument("--kernel-hash", action="store_true",
                     help="print the hash of the kernel sources that a counter summary records")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -396,6 +424,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.copy_ceiling:
+        print(json.dumps({"copy_ceiling": copy_ceiling()}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs one GPU only: the hot path here is a single-GPU lattice "
