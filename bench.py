@@ -461,6 +461,11 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
         "energy_start_end": [g["E0"], g["E1"]],
     }
+    if cfg["prec"] == "f32" and cfg["shape"] == (256, 256, 256):
+        # context for the roofline: plain copies of the same 15 fields
+        cc = copy_ceiling()
+        out["roofline"]["copy_ceiling_GBs"] = cc["TB_per_s"] * 1e3
+        out["roofline"]["frac_of_copy_ceiling"] = achieved / (cc["TB_per_s"] * 1e3)
     if not args.no_precision and cfg["prec"] == "f32":
         print("[bench] precision form", file=sys.stderr, flush=True)
         out["precision"] = precision_leg(cfg)
