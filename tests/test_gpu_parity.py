@@ -546,11 +546,19 @@ def _sampled_sites(p, rng, n):
     return np.unique(sites)
 
 
-@pytest.mark.parametrize("which", ["colloid_slab128_f64", "multi_colloid256_f32"])
+@pytest.mark.parametrize("which", ["colloid_slab128_f64", "colloid_slab128_f32", "multi_colloid256_f32",
+                                   "patterned_wall128_f32"])
 def test_full_size_forces_sampled(ora, which):
-    """Full workload sizes: GPU forces at sampled sites (random plus boundary)
-    against the oracle evaluated at those sites only."""
-    cfg = synth.colloid_slab(128) if which.startswith("colloid") else synth.multi_colloid(256)
+    """Full workload sizes (and the patterned wall at 128^3, the 512^3
+    workload's geometry and term set on wide L2/L3 tiles): GPU forces at
+    sampled sites (random plus boundary) against the oracle evaluated at
+    those sites only."""
+    if which.startswith("colloid"):
+        cfg = synth.colloid_slab(128)
+    elif which.startswith("patterned"):
+        cfg = synth.patterned_wall(128, pitch=32)
+    else:
+        cfg = synth.multi_colloid(256)
     prec = "f64" if which.endswith("f64") else "f32"
     say(f"[full size] {which}")
     p = ora.Problem(cfg["shape"], cfg["periodic"], L1=cfg["L1"], L2=cfg["L2"], L3=cfg["L3"],
