@@ -625,6 +625,11 @@ __device__ __forceinline__ void ring_pos(int r, int& px, int& py) {
     else { px = PX - 1; py = r - 2 * PX - (PY - 2) + 1; }
 }
 
+#ifndef LQ_PREFETCH
+#define LQ_PREFETCH 1
+#endif
+static_assert(LQ_PREFETCH == 1 || LQ_PREFETCH == 2, "prefetch depth is 1 or 2 planes");
+
 template <typename T, bool L23, int MODE, bool BULK, int W>
 __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_in,
                                       const T* __restrict__ v_in, const T* __restrict__ F_in,
@@ -635,6 +640,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                                       uint64_t plane_bulk) {
     using G = Tile<T, L23, W>;
     constexpr int NS = 4;
+    constexpr int PF = LQ_PREFETCH;  // planes of raw data in flight
     constexpr int TX = G::X, NTHREADS = G::N, RING = G::RING;
     constexpr int RING_ITEMS = G::RING_ITEMS, ITEMS_PER_THREAD = G::IPT;
     constexpr bool STEP = MODE != MODE_FORCE;
@@ -663,10 +669,12 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
             it_sxy[j] = (wx >= 0 && wy >= 0) ? wx + L.nx * wy : -1;
         }
     }
-    // raw data of the next plane to drift
-    T rq[5], rv[5], rf[5];
-    T iq[ITEMS_PER_THREAD], iv[ITEMS_PER_THREAD], iF[ITEMS_PER_THREAD];
-    uint32_t rm = 0, im[ITEMS_PER_THREAD];
+    // raw data of a plane still to drift (PF planes are in flight)
+    struct Raw {
+        T q[5], v[5], f[5];
+        T iq[ITEMS_PER_THREAD], iv[ITEMS_PER_THREAD], iF[ITEMS_PER_THREAD];
+        uint32_t m, im[ITEMS_PER_THREAD];
+    };
 
     const uint32_t cs = (uint32_t)N * (uint32_t)sizeof(T);  // bytes per component
     const uint32_t fb = 5u * cs;                               // bytes per field
@@ -681,72 +689,72 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
     // Branch-free loads: an invalid position gets an offset past the end of the
     // buffer instead of a branch, so the wait counts stay exact and the stores
     // of the previous plane can drain while this plane is drifted.
-    auto load = [&](int i) {
+    auto load = [&](int i, Raw& R) {
         const int wz = (i >= 0 && i <= zc + 1) ? wrapc(z0 - 1 + i, L.nz, L.per[2]) : -1;
         const bool ok = sxy_own >= 0 && wz >= 0;
         const uint32_t site = (uint32_t)(sxy_own + nxy * wz);
         const uint32_t off = ok ? site * (uint32_t)sizeof(T) : NONE;
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            rq[c] = bld<T>(rq_in, off, c * cs);
-            if (USES_V) rv[c] = bld<T>(rv_in, off, c * cs);
-            if (STEP) rf[c] = bld<T>(rF_in, off, c * cs);
+            R.q[c] = bld<T>(rq_in, off, c * cs);
+            if (USES_V) R.v[c] = bld<T>(rv_in, off, c * cs);
+            if (STEP) R.f[c] = bld<T>(rF_in, off, c * cs);
         }
-        if (!BULK) rm = __builtin_amdgcn_raw_buffer_load_b8(rmask, (int)(ok ? site : NONE), 0, 0);
+        if (!BULK) R.m = __builtin_amdgcn_raw_buffer_load_b8(rmask, (int)(ok ? site : NONE), 0, 0);
 #pragma unroll
         for (int j = 0; j < ITEMS_PER_THREAD; ++j) {
             const bool okj = it_sxy[j] >= 0 && wz >= 0;
             const uint32_t t = (uint32_t)(it_sxy[j] + nxy * wz);
             const uint32_t offj = okj ? ((uint32_t)it_c[j] * (uint32_t)N + t) * (uint32_t)sizeof(T) : NONE;
-            iq[j] = bld<T>(rq_in, offj, 0u);
-            if (USES_V) iv[j] = bld<T>(rv_in, offj, 0u);
-            if (STEP) iF[j] = bld<T>(rF_in, offj, 0u);
-            if (!BULK) im[j] = __builtin_amdgcn_raw_buffer_load_b8(rmask, (int)(okj && it_c[j] == 0 ? t : NONE), 0, 0);
+            R.iq[j] = bld<T>(rq_in, offj, 0u);
+            if (USES_V) R.iv[j] = bld<T>(rv_in, offj, 0u);
+            if (STEP) R.iF[j] = bld<T>(rF_in, offj, 0u);
+            if (!BULK) R.im[j] = __builtin_amdgcn_raw_buffer_load_b8(rmask, (int)(okj && it_c[j] == 0 ? t : NONE), 0, 0);
         }
     };
     // drift the registers into LDS slot; returns the own site's q' and v1
     // (FIRE: v after the first half kick; Nesterov: m')
-    auto drift = [&](int slot, T qn[5], T v1[5], uint32_t& m) {
+    auto drift = [&](const Raw& R, int slot, T qn[5], T v1[5], uint32_t& m) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             T x;
             if (MODE == MODE_FIRE) {
-                const T vm = fma_t(cv, rv[c], cF * rf[c]);
-                v1[c] = fma_t(hdt, rf[c], vm);
-                qn[c] = fma_t(dt, v1[c], rq[c]);
+                const T vm = fma_t(cv, R.v[c], cF * R.f[c]);
+                v1[c] = fma_t(hdt, R.f[c], vm);
+                qn[c] = fma_t(dt, v1[c], R.q[c]);
                 x = qn[c];
             } else if (MODE == MODE_GD) {
-                qn[c] = fma_t(dt, rf[c], rq[c]);
+                qn[c] = fma_t(dt, R.f[c], R.q[c]);
                 v1[c] = T(0);
                 x = qn[c];
             } else if (MODE == MODE_NAG) {
-                v1[c] = fma_t(cv, rv[c], dt * rf[c]);
-                qn[c] = rq[c] + v1[c];
+                v1[c] = fma_t(cv, R.v[c], dt * R.f[c]);
+                qn[c] = R.q[c] + v1[c];
                 x = fma_t(cv, v1[c], qn[c]);
             } else {
-                qn[c] = rq[c];
+                qn[c] = R.q[c];
                 v1[c] = T(0);
                 x = qn[c];
             }
             sq[slot][c][ty + 1][tx + 1] = x;
         }
-        m = BULK ? (uint32_t)M_FULL : rm;
-        if (!BULK) sm[slot][ty + 1][tx + 1] = (uint8_t)rm;
+        m = BULK ? (uint32_t)M_FULL : R.m;
+        if (!BULK) sm[slot][ty + 1][tx + 1] = (uint8_t)R.m;
 #pragma unroll
         for (int j = 0; j < ITEMS_PER_THREAD; ++j) {
             if (it_c[j] < 0) continue;
-            T x = iq[j];
+            T x = R.iq[j];
             if (MODE == MODE_FIRE) {
-                const T vm = fma_t(cv, iv[j], cF * iF[j]);
-                x = fma_t(dt, fma_t(hdt, iF[j], vm), x);
+                const T vm = fma_t(cv, R.iv[j], cF * R.iF[j]);
+                x = fma_t(dt, fma_t(hdt, R.iF[j], vm), x);
             } else if (MODE == MODE_GD) {
-                x = fma_t(dt, iF[j], x);
+                x = fma_t(dt, R.iF[j], x);
             } else if (MODE == MODE_NAG) {
-                const T mj = fma_t(cv, iv[j], dt * iF[j]);
+                const T mj = fma_t(cv, R.iv[j], dt * R.iF[j]);
                 x = fma_t(cv, mj, x + mj);
             }
             sq[slot][it_c[j]][it_py[j]][it_px[j]] = x;
-            if (!BULK && it_c[j] == 0) sm[slot][it_py[j]][it_px[j]] = (uint8_t)im[j];
+            if (!BULK && it_c[j] == 0) sm[slot][it_py[j]][it_px[j]] = (uint8_t)R.im[j];
         }
     };
     auto slot_of = [](int i) { return (i + NS) & (NS - 1); };
@@ -765,23 +773,16 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
     uint32_t m_older = 0, m_newer = 0;
 #pragma unroll
     for (int c = 0; c < 5; ++c) { v1_older[c] = T(0); v1_newer[c] = T(0); q_older[c] = T(0); q_newer[c] = T(0); }
-    load(0);
-    __builtin_amdgcn_sched_barrier(0);  // keep the dropped stores behind the loads
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        bst<T>(rF_out, NONE, c * cs, T(0));
-        if (STEP) bst<T>(rq_out, NONE, c * cs, T(0));
-        if (USES_V) bst<T>(rv_out, NONE, c * cs, T(0));
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma clang loop unroll(disable)
-    for (int j = 0; j <= zc + 1; ++j) {
+    // One iteration of the march: drift plane j from R (loaded PF iterations
+    // earlier), reload R with plane j + PF, and evaluate and store the force of
+    // plane j - 1 from the LDS planes j - 2 .. j.
+    auto plane = [&](int j, Raw& R) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) { v1_older[c] = v1_newer[c]; q_older[c] = q_newer[c]; }
         m_older = m_newer;
-        drift(slot_of(j), q_newer, v1_newer, m_newer);
+        drift(R, slot_of(j), q_newer, v1_newer, m_newer);
         __builtin_amdgcn_sched_barrier(0);
-        load(j + 1);
+        load(j + PF, R);
         __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of this plane's stores
         lds_barrier();
         {
@@ -808,7 +809,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
             } else {
                 site_force<T, L23, BULK, W>(P, m_older, L, s, F);
             }
-#pragma unroll
+    #pragma unroll
             for (int c = 0; c < 5; ++c) {
                 const T Fc = live ? F[c] : T(0);
                 if (MODE == MODE_FIRE || MODE == MODE_NAG) {
@@ -833,6 +834,27 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                     bst<T>(rF_out, off, c * cs, Fc);
                 }
             }
+        }
+    };
+    Raw RA, RB;
+    load(0, RA);
+    if (PF == 2) load(1, RB);
+    __builtin_amdgcn_sched_barrier(0);  // keep the dropped stores behind the loads
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        bst<T>(rF_out, NONE, c * cs, T(0));
+        if (STEP) bst<T>(rq_out, NONE, c * cs, T(0));
+        if (USES_V) bst<T>(rv_out, NONE, c * cs, T(0));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (PF == 1) {
+#pragma clang loop unroll(disable)
+        for (int j = 0; j <= zc + 1; ++j) plane(j, RA);
+    } else {
+#pragma clang loop unroll(disable)
+        for (int j = 0; j <= zc + 1; j += 2) {
+            plane(j, RA);
+            if (j + 1 <= zc + 1) plane(j + 1, RB);
         }
     }
 }
