@@ -152,6 +152,11 @@ def test_error_codes_on_the_host():
     p = lqfire.make_params(box, L6=0.1)
     h = Cc.c_void_p()
     assert lqfire.lib().lq_lattice_create(Cc.byref(p), None, Cc.byref(h)) == lqfire.LQ_EUNSUPPORTED
+    # a field of 5 N values must fit 32-bit buffer offsets: 512^3 FP64 and 600^3 FP32 are refused
+    for shape, prec in (((512, 512, 512), lqfire.LQ_F64), ((600, 600, 600), lqfire.LQ_F32)):
+        p = lqfire.make_params(shape, prec=prec)
+        assert lqfire.lib().lq_lattice_create(Cc.byref(p), None, Cc.byref(h)) == lqfire.LQ_EINVAL
+        assert b"2^32" in lqfire.lib().lq_last_error(None)
     p = lqfire.make_params((8, 8, 8), prec=lqfire.LQ_F32)
     p.prec = 7
     assert lqfire.lib().lq_lattice_create(Cc.byref(p), None, Cc.byref(h)) == lqfire.LQ_EINVAL
