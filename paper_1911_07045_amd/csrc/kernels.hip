@@ -318,18 +318,61 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
     // external fields: a constant force per simulated site
 #pragma unroll
     for (int c = 0; c < 5; ++c) g[c] -= T(L.ext[c]);
-    if (BULK && !L23) {
+    if (BULK) {
         // every bond has weight 1: the L1 term is -L1 M (sum of neighbours - 6 q)
+        T S[3][5];  // q(+e_k) + q(-e_k)
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            T lap = ((P.at(1, 0, 0, c) + P.at(-1, 0, 0, c)) + (P.at(0, 1, 0, c) + P.at(0, -1, 0, c)))
-                    + (P.at(0, 0, 1, c) + P.at(0, 0, -1, c));
-            F[c] = fma_t(T(-6), q0[c], lap);
+            S[0][c] = P.at(1, 0, 0, c) + P.at(-1, 0, 0, c);
+            S[1][c] = P.at(0, 1, 0, c) + P.at(0, -1, 0, c);
+            S[2][c] = P.at(0, 0, 1, c) + P.at(0, 0, -1, c);
+            F[c] = fma_t(T(-6), q0[c], (S[0][c] + S[1][c]) + S[2][c]);
         }
         T o[5];
         metric(F, o);
 #pragma unroll
         for (int c = 0; c < 5; ++c) g[c] = fma_t(-L1, o[c], g[c]);
+        if (L23) {
+            // In the bulk every mean difference is central and both L2/L3
+            // parts depend on L2 + L3 only.  Same-axis part: (L2 + L3) times
+            // the sum over axes k of column k of (2 q - S_k).  Cross-axis
+            // part: the sum over x = centre -+ e_j of +-1/2 h_j(x) collapses
+            // to -1/4 (L2 + L3) sum_{j<k} X_jk, where X_jk = P^T H with
+            // H_aj = D_ak, H_ak = D_aj, and D the full tensor of the mixed
+            // second difference q(+j+k) - q(+j-k) - q(-j+k) + q(-j-k).
+            // Written out, X_xy = (D1, D0 + D3, D4, D1, D2),
+            // X_xz = (0, D4, -D3, -D2, D1), X_yz = (-D4, D2, D1, 0, -D0).
+            T d[3][5];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) d[k][c] = fma_t(T(2), q0[c], -S[k][c]);
+            const T s2 = d[2][0] + d[2][3];
+            T col[5];
+            col[0] = d[0][0] + s2;
+            col[1] = d[0][1] + d[1][1];
+            col[2] = d[0][2] + d[2][2];
+            col[3] = d[1][3] + s2;
+            col[4] = d[1][4] + d[2][4];
+            auto mix = [&](int j, int k, int c) {
+                int pj[3], pk[3];
+                unit(j, 1, pj[0], pj[1], pj[2]);
+                unit(k, 1, pk[0], pk[1], pk[2]);
+                return (P.at(pj[0] + pk[0], pj[1] + pk[1], pj[2] + pk[2], c) -
+                        P.at(pj[0] - pk[0], pj[1] - pk[1], pj[2] - pk[2], c)) -
+                       (P.at(pk[0] - pj[0], pk[1] - pj[1], pk[2] - pj[2], c) -
+                        P.at(-pj[0] - pk[0], -pj[1] - pk[1], -pj[2] - pk[2], c));
+            };
+            T X[5];
+            X[0] = mix(0, 1, 1) - mix(1, 2, 4);
+            X[1] = (mix(0, 1, 0) + mix(0, 1, 3)) + (mix(0, 2, 4) + mix(1, 2, 2));
+            X[2] = (mix(0, 1, 4) - mix(0, 2, 3)) + mix(1, 2, 1);
+            X[3] = mix(0, 1, 1) - mix(0, 2, 2);
+            X[4] = (mix(0, 1, 2) + mix(0, 2, 1)) - mix(1, 2, 0);
+            const T L23s = T(L.L2) + T(L.L3);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) g[c] = fma_t(L23s, fma_t(T(-0.25), X[c], col[c]), g[c]);
+        }
     } else {
         // bond sums: L1 and the same-axis part of L2/L3
 #pragma unroll
@@ -354,39 +397,6 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
 #pragma unroll
                     for (int c = 0; c < 5; ++c) g[c] = fma_t(wl23, o[c], g[c]);
                 }
-            }
-    }
-    if (L23 && BULK) {
-        // cross-axis part in the bulk, where every mean difference is central:
-        // sum over x = centre -+ e_j of +-1/2 h_j(x) collapses to
-        // -1/4 sum_{j<k} (M_jk + M_kj) D_jk, with D_jk the mixed second
-        // difference q(+j+k) - q(+j-k) - q(-j+k) + q(-j-k) and M_jk the map
-        // from C_k to h_j (cross_h with only C_k set)
-        const T L2 = T(L.L2), L3 = T(L.L3);
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int k = j + 1; k < 3; ++k) {
-                int pj[3], pk[3];
-                unit(j, 1, pj[0], pj[1], pj[2]);
-                unit(k, 1, pk[0], pk[1], pk[2]);
-                T C1[3][5], C2[3][5], h1[5], h2[5];
-#pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    const T d = (P.at(pj[0] + pk[0], pj[1] + pk[1], pj[2] + pk[2], c) -
-                                 P.at(pj[0] - pk[0], pj[1] - pk[1], pj[2] - pk[2], c)) -
-                                (P.at(pk[0] - pj[0], pk[1] - pj[1], pk[2] - pj[2], c) -
-                                 P.at(-pj[0] - pk[0], -pj[1] - pk[1], -pj[2] - pk[2], c));
-#pragma unroll
-                    for (int m = 0; m < 3; ++m) {
-                        C1[m][c] = m == k ? d : T(0);
-                        C2[m][c] = m == j ? d : T(0);
-                    }
-                }
-                cross_h(j, C1, L2, L3, h1);
-                cross_h(k, C2, L2, L3, h2);
-#pragma unroll
-                for (int c = 0; c < 5; ++c) g[c] = fma_t(T(-0.25), h1[c] + h2[c], g[c]);
             }
     }
     if (L23 && !BULK) {
