@@ -309,7 +309,7 @@ __device__ __forceinline__ void mean_diffs(const Stencil<T, L23, BULK, W>& P, in
 // -dE/dq at the stencil centre (a simulated site with mask m0).
 template <typename T, bool L23, bool BULK, int W>
 __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, uint32_t m0,
-                                           const LatDev& L, int site, T F[5]) {
+                                           const LatDev& L, int arow1, T F[5]) {
     const T A = T(L.A), B = T(L.B), C = T(L.C), L1 = T(L.L1);
     T q0[5];
     P.load5(0, 0, 0, q0);
@@ -467,11 +467,8 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
         }
     }
     if (!BULK && (m0 & M_ANCH)) {
-        // row of the site's anchoring form; the range-checked load gives 0
-        // (no anchoring) for a site index outside the lattice
-        const __amdgpu_buffer_rsrc_t ri = field_rsrc(L.anch_index, (uint32_t)L.N * 4u);
-        const int at = (int)__builtin_amdgcn_raw_buffer_load_b32(
-                           ri, (int)(site >= 0 ? (uint32_t)site * 4u : 0xFFFFFFFFu), 0, 0) - 1;
+        // row of the site's anchoring form (arow1 = 1 + row, 0: none)
+        const int at = arow1 - 1;
         if (at >= 0) {
             // d/dq of 1/2 q^T K q + b^T q = K q + b, K from its upper triangle
             const double* d = L.anch_data + ANCH_STRIDE * (int64_t)at;
@@ -781,16 +778,28 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
     // evaluated in this iteration, `newer` the plane just drifted.
     T v1_older[5], v1_newer[5], q_older[5], q_newer[5];
     uint32_t m_older = 0, m_newer = 0;
+    // anchoring row (1 + row, 0: none) of the own site: loaded right after
+    // the drift, once the mask is known, so that it has arrived by the time
+    // the force of that plane is evaluated in the next iteration
+    const __amdgpu_buffer_rsrc_t ranch = field_rsrc(L.anch_index, (uint32_t)N * 4u);
+    int a_older = 0, a_newer = 0;
 #pragma unroll
     for (int c = 0; c < 5; ++c) { v1_older[c] = T(0); v1_newer[c] = T(0); q_older[c] = T(0); q_newer[c] = T(0); }
     // One iteration of the march: drift plane j from R (loaded PF iterations
     // earlier), reload R with plane j + PF, and evaluate and store the force of
     // plane j - 1 from the LDS planes j - 2 .. j.
+    T fmax_abs = T(0);  // max |F| in the field's own type (exact), folded into red[3] at the end
     auto plane = [&](int j, Raw& R) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) { v1_older[c] = v1_newer[c]; q_older[c] = q_newer[c]; }
         m_older = m_newer;
+        a_older = a_newer;
         drift(R, slot_of(j), q_newer, v1_newer, m_newer);
+        if (!BULK) {
+            const bool anch = own_xy && j >= 1 && j <= zc && (m_newer & M_ANCH);
+            const uint32_t sj = (uint32_t)(gx + L.nx * gy + nxy * (z0 + j - 1));
+            a_newer = (int)__builtin_amdgcn_raw_buffer_load_b32(ranch, (int)(anch ? sj * 4u : NONE), 0, 0);
+        }
         __builtin_amdgcn_sched_barrier(0);
         load(j + PF, R);
         __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of this plane's stores
@@ -815,9 +824,9 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                 PB.q = sq; PB.m = sm;
                 PB.s[0] = P.s[0]; PB.s[1] = P.s[1]; PB.s[2] = P.s[2];
                 PB.cx = P.cx; PB.cy = P.cy;
-                site_force<T, L23, true, W>(PB, (uint32_t)M_FULL, L, s, F);
+                site_force<T, L23, true, W>(PB, (uint32_t)M_FULL, L, 0, F);
             } else {
-                site_force<T, L23, BULK, W>(P, m_older, L, s, F);
+                site_force<T, L23, BULK, W>(P, m_older, L, a_older, F);
             }
     #pragma unroll
             for (int c = 0; c < 5; ++c) {
@@ -832,14 +841,14 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                     red[0] = fma(fd, vd, red[0]);
                     red[1] = fma(fd, fd, red[1]);
                     red[2] = fma(vd, vd, red[2]);
-                    red[3] = fmax(red[3], fabs(fd));
+                    fmax_abs = fmax(fmax_abs, fabs(Fc));
                 } else if (MODE == MODE_GD) {
                     const T qc = live ? P.at(0, 0, 0, c) : T(0);
                     bst<T>(rq_out, off, c * cs, qc);
                     bst<T>(rF_out, off, c * cs, Fc);
                     const double fd = (double)Fc;
                     red[1] = fma(fd, fd, red[1]);
-                    red[3] = fmax(red[3], fabs(fd));
+                    fmax_abs = fmax(fmax_abs, fabs(Fc));
                 } else {
                     bst<T>(rF_out, off, c * cs, Fc);
                 }
@@ -867,6 +876,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
             if (j + 1 <= zc + 1) plane(j + 1, RB);
         }
     }
+    red[3] = fmax(red[3], (double)fmax_abs);
 }
 
 // One block of the force / FIRE step: tile `bid` of lattice L.  `nblocks`
