@@ -31,6 +31,7 @@ struct lq_lattice {
     uint64_t* d_tile_planes = nullptr;
     int32_t* d_anch_index = nullptr;
     double* d_anch_data = nullptr;
+    void* d_anch_force = nullptr;  // K upper triangle and b of each row, in the field's element type
     int n_anch = 0;
     // energy scratch
     double* d_epart = nullptr;
@@ -207,10 +208,12 @@ static void free_geometry(lq_lattice* lat) {
     if (lat->d_tile_planes) (void)hipFree(lat->d_tile_planes);
     if (lat->d_anch_index) (void)hipFree(lat->d_anch_index);
     if (lat->d_anch_data) (void)hipFree(lat->d_anch_data);
+    if (lat->d_anch_force) (void)hipFree(lat->d_anch_force);
     lat->d_mask = lat->d_tile = nullptr;
     lat->d_tile_planes = nullptr;
     lat->d_anch_index = nullptr;
     lat->d_anch_data = nullptr;
+    lat->d_anch_force = nullptr;
 }
 
 // Uploads a rasterized geometry and refreshes the device view.
@@ -250,6 +253,23 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
         HIPCHK(lat, hipMalloc(&lat->d_anch_data, g.anch_data.size() * sizeof(double)));
         HIPCHK(lat, hipMemcpy(lat->d_anch_data, g.anch_data.data(), g.anch_data.size() * sizeof(double),
                               hipMemcpyHostToDevice));
+        // the force needs K and b only: ANCH_FSTRIDE values per row, rounded
+        // to the field's element type once here
+        const size_t rows = g.anch_site.size();
+        if (lat->p.prec == LQ_F64) {
+            std::vector<double> f(rows * ANCH_FSTRIDE);
+            for (size_t i = 0; i < rows; ++i)
+                for (int k = 0; k < ANCH_FSTRIDE; ++k) f[i * ANCH_FSTRIDE + k] = g.anch_data[i * ANCH_STRIDE + k];
+            HIPCHK(lat, hipMalloc(&lat->d_anch_force, f.size() * sizeof(double)));
+            HIPCHK(lat, hipMemcpy(lat->d_anch_force, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> f(rows * ANCH_FSTRIDE);
+            for (size_t i = 0; i < rows; ++i)
+                for (int k = 0; k < ANCH_FSTRIDE; ++k)
+                    f[i * ANCH_FSTRIDE + k] = (float)g.anch_data[i * ANCH_STRIDE + k];
+            HIPCHK(lat, hipMalloc(&lat->d_anch_force, f.size() * sizeof(float)));
+            HIPCHK(lat, hipMemcpy(lat->d_anch_force, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
     }
     d.mask = lat->d_mask;
     d.tile_bulk = lat->d_tile;
@@ -257,6 +277,7 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     d.n_anch = lat->n_anch;
     d.anch_index = lat->d_anch_index;
     d.anch_data = lat->d_anch_data;
+    d.anch_force = lat->d_anch_force;
     lat->n_sim = g.n_sim;
     lat->bound = false;
     return LQ_OK;

@@ -306,10 +306,50 @@ __device__ __forceinline__ void mean_diffs(const Stencil<T, L23, BULK, W>& P, in
     }
 }
 
-// -dE/dq at the stencil centre (a simulated site with mask m0).
+// K (upper triangle) and b of one site's anchoring form
+template <typename T>
+struct AnchRow {
+    T k[15], b[5];
+};
+
+// Loads the force's copy of anchoring row arow1 - 1 (zeros for arow1 == 0:
+// the offset lies past the end of the buffer).
+template <typename T>
+__device__ __forceinline__ void anch_load(const LatDev& L, int arow1, AnchRow<T>& A) {
+    constexpr uint32_t ROW = ANCH_FSTRIDE * sizeof(T);  // 80 or 160 bytes: whole 16-byte pieces
+    const __amdgpu_buffer_rsrc_t r = field_rsrc(L.anch_force, (uint32_t)L.n_anch * ROW);
+    const uint32_t off = arow1 > 0 ? (uint32_t)(arow1 - 1) * ROW : 0xFFFFFFFFu;
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    T v[ANCH_FSTRIDE];
+#pragma unroll
+    for (int i = 0; i < (int)(ROW / 16); ++i) {
+        // whole-vector casts: a bit cast of one subscripted element of the
+        // loaded vector is not reliably compiled
+        const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, i * 16, 0);
+        if constexpr (sizeof(T) == 4) {
+            const f32x4 x = __builtin_bit_cast(f32x4, w);
+            v[4 * i + 0] = x.x; v[4 * i + 1] = x.y; v[4 * i + 2] = x.z; v[4 * i + 3] = x.w;
+        } else {
+            const f64x2 x = __builtin_bit_cast(f64x2, w);
+            v[2 * i + 0] = x.x; v[2 * i + 1] = x.y;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 15; ++i) A.k[i] = v[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) A.b[i] = v[15 + i];
+}
+
+// -dE/dq at the stencil centre (a simulated site with mask m0).  Where m0
+// carries the anchoring bit, the site's anchoring form is AR (wide tiles,
+// loaded ahead by the caller) or row arow1 - 1 of the FP64 forms, read here
+// (narrow tiles: on the serving stream of small boxes this measured a lower
+// tail latency than the early loads).
 template <typename T, bool L23, bool BULK, int W>
 __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, uint32_t m0,
-                                           const LatDev& L, int arow1, T F[5]) {
+                                           const LatDev& L, const AnchRow<T>& AR, int arow1, T F[5]) {
     const T A = T(L.A), B = T(L.B), C = T(L.C), L1 = T(L.L1);
     T q0[5];
     P.load5(0, 0, 0, q0);
@@ -466,11 +506,27 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
             }
         }
     }
-    if (!BULK && (m0 & M_ANCH)) {
-        // row of the site's anchoring form (arow1 = 1 + row, 0: none)
+    // d/dq of 1/2 q^T K q + b^T q = K q + b, K from its upper triangle
+    if (!BULK && W == 1 && (m0 & M_ANCH)) {
+        T Kq[5];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) Kq[a] = AR.b[a];
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int b = a; b < 5; ++b, ++t) {
+                const T k = AR.k[t];
+                Kq[a] = fma_t(k, q0[b], Kq[a]);
+                if (b != a) Kq[b] = fma_t(k, q0[a], Kq[b]);
+            }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) g[c] += Kq[c];
+    }
+    if (!BULK && W == 0 && (m0 & M_ANCH)) {
+        // narrow tiles: the row of the FP64 form, read here
         const int at = arow1 - 1;
         if (at >= 0) {
-            // d/dq of 1/2 q^T K q + b^T q = K q + b, K from its upper triangle
             const double* d = L.anch_data + ANCH_STRIDE * (int64_t)at;
             T Kq[5];
 #pragma unroll
@@ -790,6 +846,17 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
     // plane j - 1 from the LDS planes j - 2 .. j.
     T fmax_abs = T(0);  // max |F| in the field's own type (exact), folded into red[3] at the end
     auto plane = [&](int j, Raw& R) {
+        // anchoring forms of plane j - 1, whose force this iteration
+        // evaluates.  Wide tiles issue them first, so that they arrive while
+        // plane j is drifted and the block meets at the barrier.  Narrow tiles
+        // (the small boxes of a batch) load them just before the force: the
+        // registers held across the drift would spill there.
+        AnchRow<T> A;
+        if (!BULK && W == 1) {
+            const int f = j - 1;
+            const bool bulk_plane = f >= 1 && f <= 64 && ((plane_bulk >> (f - 1)) & 1);
+            if (!bulk_plane) anch_load(L, (m_newer & M_ANCH) ? a_newer : 0, A);
+        }
 #pragma unroll
         for (int c = 0; c < 5; ++c) { v1_older[c] = v1_newer[c]; q_older[c] = q_newer[c]; }
         m_older = m_newer;
@@ -824,9 +891,9 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                 PB.q = sq; PB.m = sm;
                 PB.s[0] = P.s[0]; PB.s[1] = P.s[1]; PB.s[2] = P.s[2];
                 PB.cx = P.cx; PB.cy = P.cy;
-                site_force<T, L23, true, W>(PB, (uint32_t)M_FULL, L, 0, F);
+                site_force<T, L23, true, W>(PB, (uint32_t)M_FULL, L, A, 0, F);
             } else {
-                site_force<T, L23, BULK, W>(P, m_older, L, a_older, F);
+                site_force<T, L23, BULK, W>(P, m_older, L, A, a_older, F);
             }
     #pragma unroll
             for (int c = 0; c < 5; ++c) {

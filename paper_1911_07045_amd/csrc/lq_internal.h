@@ -21,6 +21,9 @@ constexpr uint8_t M_FULL = 0x7F;  // simulated bulk site with all six neighbours
 // Anchoring form of one site: upper triangle of K (15), b (5), c (1) with
 // f = 1/2 q^T K q + b^T q + c.
 constexpr int ANCH_STRIDE = 21;
+// The force's copy of a row: K upper triangle (15) and b (5), in the field's
+// element type.
+constexpr int ANCH_FSTRIDE = 20;
 
 // Host-side rasterization result.
 struct Geometry {
@@ -126,6 +129,7 @@ struct LatDev {
     int n_anch;
     const int32_t* anch_index;  // per site: 1 + row of anch_data, 0 when not anchored
     const double* anch_data;    // ANCH_STRIDE per anchored site
+    const void* anch_force;     // ANCH_FSTRIDE per anchored site, element type of the field
     double ext[5];              // constant external-field force per simulated site
     double A, B, C, L1, L2, L3, L4;
     int zc, ntx, nty, ntz;
