@@ -85,6 +85,17 @@ CASES = {
         dict(kind="wall", axis=2, plane=0, law="nd", W=0.5, dir=(1.0, 0.0, 0.0)),
         dict(kind="wall", axis=2, plane=11, law="fg", W=0.7),
         dict(kind="sphere", center=(14.2, 9.1, 5.5), radius=3.3, law="rp", W=5.0, dir="normal")]),
+    # wide tiles in every precision (x at least one wide tile), with anchored
+    # sites inside tiles whose other planes take the bulk evaluation
+    "wide_spheres_wall_records_L1": dict(shape=(136, 12, 20), objects=[
+        dict(kind="sphere", center=(40.3, 5.5, 9.7), radius=4.5, law="rp", W=4.0, dir="normal"),
+        dict(kind="sphere", center=(110.0, 6.0, 1.0), radius=3.2, law="nd", W=0.8, dir="normal"),
+        dict(kind="wall", axis=2, plane=15, law="nd", W=0.6, dir=(0.0, 0.6, 0.8))],
+        records=[dict(site=5000, law="fg", W=0.5, nu=(0.0, 0.0, 1.0)), dict(site=5000, law="rp", W=2.0, n0=(1, 0, 0)),
+                 dict(site=30000, law="nd", W=1.5, n0=(0.0, 1.0, 0.0))]),
+    "wide_colloid_walls_L23": dict(shape=(70, 10, 14), periodic=(True, True, False), L2=1.16, L3=0.7, objects=[
+        dict(kind="wall", axis=2, plane=0, law="nd", W=0.5, dir=(1.0, 0.0, 0.0)),
+        dict(kind="sphere", center=(66.5, 4.0, 7.2), radius=3.6, law="rp", W=6.0, dir="normal")]),
     "sandwiched_plane_L23": dict(shape=(66, 5, 3), L2=1.16, L3=0.3, objects=[
         dict(kind="wall", axis=2, plane=0, law="nd", W=0.7, dir=(0.0, 1.0, 0.0)),
         dict(kind="wall", axis=2, plane=2, law="nd", W=0.2, dir="normal")]),
@@ -114,7 +125,8 @@ def test_forces_and_energy_fp64(ora, name):
 
 @pytest.mark.parametrize("name", ["bulk32_L1", "ragged_periodic_L23", "colloid_slab24_L23",
                                   "patterned_records_L23", "fg_walls_sphere_field_L23",
-                                  "chiral_L234_walls_colloid_open"])
+                                  "chiral_L234_walls_colloid_open", "wide_spheres_wall_records_L1",
+                                  "wide_colloid_walls_L23"])
 def test_forces_and_energy_fp32(ora, name):
     c = dict(CASES[name])
     say(f"[forces f32] {name} {c['shape']}")
