@@ -121,7 +121,9 @@ typedef struct {
  * unit vector from a sphere's centre) and ignores dir_mode and the patterned
  * wall's radial director (sec. II.A.4).  Host arrays; any may be NULL
  * when its count is 0.  LQ_EINVAL on a bad object, a record at an object site
- * or out of range, or S0 not real while anchoring is requested. */
+ * or out of range, S0 not real while anchoring is requested, or more anchored
+ * sites than the kernels address (53687091 in FP32, 26843545 in FP64); the
+ * previous geometry then stays in place. */
 int lq_set_boundaries(lq_lattice* lat, const lq_object* objs, int32_t n_objs,
                       const lq_site_anchor* recs, int64_t n_recs,
                       const int64_t* object_sites, int64_t n_object_sites);

@@ -374,6 +374,10 @@ int lq_set_boundaries(lq_lattice* lat, const lq_object* objs, int32_t n_objs, co
     Geometry g;
     int rc = rasterize(lat->p, lat->S0, objs, n_objs, recs, n_recs, object_sites, n_object_sites, g, err);
     if (rc != LQ_OK) return fail(lat, rc, err);
+    // the step kernels address the anchoring rows (ANCH_FSTRIDE values of the
+    // field's type each) with 32-bit byte offsets
+    if ((uint64_t)g.anch_site.size() * (uint64_t)(ANCH_FSTRIDE * elem_size(lat)) > 0xFFFFFFFFull)
+        return fail(lat, LQ_EINVAL, "too many anchored sites (at most 53687091 in FP32, 26843545 in FP64)");
     return upload_geometry(lat, g);
 }
 
