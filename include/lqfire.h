@@ -66,6 +66,8 @@ typedef struct {
 /* Creates a lattice with every site bulk.  stream: a hipStream_t, or NULL for
  * the null stream.  On success *out owns device tables of ~N bytes. */
 int lq_lattice_create(const lq_params* p, void* stream, lq_lattice** out);
+/* Frees the lattice's tables after its stream's work; a member of a batch
+ * leaves the batch first.  NULL is a no-op. */
 int lq_lattice_destroy(lq_lattice* lat);
 
 /* S0 of Eq. (S0def) for the lattice's A, B, C (NaN when it has no real value). */
@@ -291,9 +293,11 @@ int lq_batch_create(int32_t capacity, void* stream, lq_batch** out);
 int lq_batch_destroy(lq_batch* b);
 
 /* Adds a lattice already bound by lq_fire_init (its stream is synchronized
- * first).  LQ_EINVAL when the batch is full, the lattice is a member already,
- * or its prec / L2-L3 use differs from the members'; LQ_ESTATE when it is not
- * bound. */
+ * first).  A lattice belongs to at most one batch.  LQ_EINVAL when the batch
+ * is full, the lattice is a member of this or another batch, or its prec /
+ * L2-L3 use differs from the members'; LQ_ESTATE when it is not bound.
+ * Destroying a member lattice removes it from its batch (after the batch's
+ * queued work); destroying a batch leaves its lattices intact. */
 int lq_batch_add(lq_batch* b, lq_lattice* lat);
 
 /* Removes a member; its buffers keep the state of its last step. */

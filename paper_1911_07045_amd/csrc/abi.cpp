@@ -17,7 +17,11 @@
 
 using namespace lq;
 
+struct lq_batch;
+static void leave_batch(lq_lattice* lat);
+
 struct lq_lattice {
+    lq_batch* batch = nullptr;  // the batch this lattice is a member of, if any
     lq_params p{};
     double S0 = NAN;
     int device = 0;
@@ -331,6 +335,7 @@ int lq_lattice_create(const lq_params* p, void* stream, lq_lattice** out) {
 
 int lq_lattice_destroy(lq_lattice* lat) {
     if (!lat) return LQ_OK;
+    leave_batch(lat);
     (void)hipSetDevice(lat->device);
     (void)hipStreamSynchronize(lat->stream);
     free_geometry(lat);
@@ -717,6 +722,21 @@ struct lq_batch {
     std::vector<int> order;      // device order -> index in members
 };
 
+// Removes a lattice that is being destroyed from its batch, after the
+// batch's queued work has finished.
+static void leave_batch(lq_lattice* lat) {
+    lq_batch* b = lat->batch;
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    for (size_t i = 0; i < b->members.size(); ++i)
+        if (b->members[i] == lat) {
+            b->members.erase(b->members.begin() + (long)i);
+            break;
+        }
+    lat->batch = nullptr;
+}
+
 static int fin_blocks_of(const lq_lattice* lat) {
     const int64_t n = 5 * lat->N;
     const int64_t b = (n + 256 * 8 - 1) / (256 * 8);
@@ -753,6 +773,7 @@ int lq_batch_destroy(lq_batch* b) {
     if (!b) return LQ_OK;
     (void)hipSetDevice(b->device);
     (void)hipStreamSynchronize(b->stream);
+    for (lq_lattice* m : b->members) m->batch = nullptr;
     if (b->d_mem) (void)hipFree(b->d_mem);
     if (b->d_tile_off) (void)hipFree(b->d_tile_off);
     if (b->d_fin_off) (void)hipFree(b->d_fin_off);
@@ -772,8 +793,8 @@ int lq_batch_add(lq_batch* b, lq_lattice* lat) {
     if (lat->method != LQ_METHOD_FIRE) return fail(lat, LQ_EINVAL, "batched stepping runs FIRE only");
     if ((int)b->members.size() >= b->capacity) return fail(lat, LQ_EINVAL, "batch is full");
     if (lat->device != b->device) return fail(lat, LQ_EINVAL, "lattice and batch are on different devices");
-    for (lq_lattice* m : b->members)
-        if (m == lat) return fail(lat, LQ_EINVAL, "lattice is a member already");
+    if (lat->batch == b) return fail(lat, LQ_EINVAL, "lattice is a member already");
+    if (lat->batch) return fail(lat, LQ_EINVAL, "lattice is a member of another batch");
     if (!b->members.empty() && (lat->p.prec != b->prec || lat->l23 != b->l23))
         return fail(lat, LQ_EINVAL, "members must share prec and the use of L2/L3");
     HIPCHK(lat, hipSetDevice(lat->device));
@@ -783,6 +804,7 @@ int lq_batch_add(lq_batch* b, lq_lattice* lat) {
         b->l23 = lat->l23;
     }
     b->members.push_back(lat);
+    lat->batch = b;
     return LQ_OK;
 }
 
@@ -791,6 +813,7 @@ int lq_batch_remove(lq_batch* b, lq_lattice* lat) {
     for (size_t i = 0; i < b->members.size(); ++i)
         if (b->members[i] == lat) {
             b->members.erase(b->members.begin() + (long)i);
+            lat->batch = nullptr;
             return LQ_OK;
         }
     return fail(lat, LQ_EINVAL, "lattice is not a member");

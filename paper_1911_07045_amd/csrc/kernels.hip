@@ -849,8 +849,9 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
         // anchoring forms of plane j - 1, whose force this iteration
         // evaluates.  Wide tiles issue them first, so that they arrive while
         // plane j is drifted and the block meets at the barrier.  Narrow tiles
-        // (the small boxes of a batch) load them just before the force: the
-        // registers held across the drift would spill there.
+        // (the small boxes of a batch) read the FP64 rows inside the force
+        // instead: on a stream of small boxes the early loads raised the tail
+        // latency.
         AnchRow<T> A;
         if (!BULK && W == 1) {
             const int f = j - 1;

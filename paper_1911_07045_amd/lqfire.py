@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblqfire.so")
@@ -247,6 +248,10 @@ class Lattice:
 
     def close(self):
         if getattr(self, "h", None):
+            b = self._batch() if getattr(self, "_batch", None) else None
+            if b is not None and self in b.members:
+                b.members.remove(self)  # the library removes it from the batch too
+            self._batch = None
             lib().lq_lattice_destroy(self.h)
             self.h = None
 
@@ -406,6 +411,9 @@ class Batch:
         if getattr(self, "h", None):
             lib().lq_batch_destroy(self.h)
             self.h = None
+            for m in self.members:
+                m._batch = None
+            self.members = []
 
     def __del__(self):
         try:
@@ -419,10 +427,12 @@ class Batch:
     def add(self, lat: Lattice):
         _check(lib().lq_batch_add(self.h, lat.h), lat.h)
         self.members.append(lat)
+        lat._batch = weakref.ref(self)
 
     def remove(self, lat: Lattice):
         _check(lib().lq_batch_remove(self.h, lat.h), lat.h)
         self.members.remove(lat)
+        lat._batch = None
 
     def step(self, n_steps):
         """Returns one FireReport per member, in member order."""

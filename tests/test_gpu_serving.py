@@ -149,3 +149,40 @@ def test_batch_mixing_narrow_and_wide_tiles_equals_alone():
     b.step(17)
     for (lat, q, v, F), (qa, va, Fa) in zip(held, alone):
         assert torch.equal(q.cpu(), qa) and torch.equal(v.cpu(), va) and torch.equal(F.cpu(), Fa)
+
+
+def test_destroying_a_member_leaves_its_batch():
+    """Closing a member lattice removes it from its batch (the batch keeps
+    stepping the others, which still follow their solo trajectories); a
+    lattice belongs to one batch at a time; closing a batch leaves its
+    lattices usable."""
+    say("[batch] member destroyed while in a batch")
+    reqs = _reqs(3, 25, force_tol=0.0, max_steps=10 ** 6)
+    alone = []
+    for r in reqs[1:]:
+        lat, q, v, F = _bound(r, "f32")
+        lat.fire_step(25)
+        alone.append((q.cpu(), v.cpu(), F.cpu()))
+        lat.close()
+    held = [_bound(r, "f32") for r in reqs]
+    b = lqfire.Batch(4)
+    for h in held:
+        b.add(h[0])
+    other = lqfire.Batch(2)
+    with pytest.raises(lqfire.LQError):
+        other.add(held[1][0])
+    b.step(10)
+    held[0][0].close()
+    assert len(b) == 2 and lqfire.lib().lq_batch_size(b.h) == 2
+    reps = b.step(15)
+    assert len(reps) == 2
+    for (lat, q, v, F), (qa, va, Fa) in zip(held[1:], alone):
+        assert torch.equal(q.cpu(), qa) and torch.equal(v.cpu(), va) and torch.equal(F.cpu(), Fa)
+    b.close()
+    other.add(held[1][0])
+    assert len(other.step(1)) == 1
+    other.close()
+    rep = held[2][0].fire_step(1)
+    assert rep.step == 26
+    for h in held[1:]:
+        h[0].close()
