@@ -168,6 +168,141 @@ def minimizer_leg(cfg, steps=300, warmup=20):
     return out
 
 
+def _random_start(lat, cfg, seed=None):
+    import numpy as np
+    import torch
+
+    from paper_1911_07045_amd import synth
+
+    dirs = torch.from_numpy(np.ascontiguousarray(
+        synth.random_directors(cfg["dir_seed"] if seed is None else seed, lat.N))).cuda()
+    return lat.set_uniaxial(dirs, lat.empty())
+
+
+def convergence_leg(n=256, prec="f32", budget_s=10.0, chunk=100):
+    """FIRE against separately tuned gradient descent (and Nesterov) on the
+    n^3 periodic bulk box from the same random start (the paper's FIRE-vs-GD
+    comparison of its minimizer section): energy above the uniform nematic
+    state and |F|/sqrt(N) against the wall-clock time spent stepping."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1911_07045_amd import lqfire, synth
+
+    cfg = synth.bulk(n, prec=prec)
+    lat = lqfire.lattice_from_config(cfg)
+    N = lat.N
+    uni = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    uni[:N] = 1.0
+    E_min = lat.energy(lat.set_uniaxial(uni, lat.empty()))["total"]
+    del uni
+
+    def run(method, dt=None, mu=0.0, budget=budget_s):
+        q = _random_start(lat, cfg)
+        v, F = lat.empty(), lat.empty()
+        if method == "fire":  # dt: the largest FIRE time step
+            lat.fire_init(lqfire.fire_params_from_config(cfg, dt_max=dt, force_tol=0.0, max_steps=1 << 62),
+                          q, v, F)
+        else:
+            lat.descent_init(lqfire.make_descent_params(method, dt, mu, force_tol=0.0, max_steps=1 << 62),
+                             q, v, F)
+        t, steps, curve = 0.0, 0, []
+        E = lat.energy(q)["total"]
+        curve.append((0.0, 0, E - E_min, float("nan")))
+        while t < budget:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                rep = lat.fire_step(chunk)
+            except lqfire.LQError as e:  # a diverging step size in the tuning sweep
+                if e.code != lqfire.LQ_ENONFINITE:
+                    raise
+                curve.append((t, steps, float("inf"), float("inf")))
+                break
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            steps += chunk
+            E = lat.energy(q)["total"]
+            if not math.isfinite(E) or rep.status == lqfire.NONFINITE:
+                curve.append((t, steps, float("inf"), float("inf")))
+                break
+            curve.append((t, steps, E - E_min, rep.normF / math.sqrt(N)))
+        del q, v, F
+        return curve
+
+    # tuning, separately for each method: the step (FIRE: its largest time
+    # step) whose run reaches the lowest energy in the same short time
+    tuned = {}
+    for method, mu, dts in (("fire", 0.0, (0.01, 0.03, 0.1, 0.2)),
+                            ("gd", 0.0, (0.005, 0.01, 0.02, 0.03, 0.04)),
+                            ("nesterov", 0.9, (0.002, 0.005, 0.01, 0.02))):
+        best = None
+        for dt in dts:
+            c = run(method, dt, mu, budget=0.5)
+            dE = c[-1][2]
+            if math.isfinite(dE) and (best is None or dE < best[1]):
+                best = (dt, dE)
+        tuned[method] = (best[0], mu)
+    out = {"workload": f"bulk{n}", "prec": prec, "E_min": E_min, "budget_s": budget_s, "chunk": chunk,
+           "tuned": {k: {"dt": v[0], "momentum": v[1]} for k, v in tuned.items()},
+           "fire_fixed": {k: cfg["fire"][k] for k in ("dt0", "alpha0")}, "methods": {}}
+    runs = [("fire", "fire") + tuned["fire"], ("fire_dtmax_0.01", "fire", 0.01, 0.0),
+            ("gd", "gd") + tuned["gd"], ("nesterov", "nesterov") + tuned["nesterov"]]
+    for name, method, dt, mu in runs:
+        c = run(method, dt, mu)
+        reach = {}
+        for thr in (1e-1, 1e-2, 1e-3, 1e-4):
+            hit = next((r for r in c[1:] if r[3] <= thr), None)
+            reach[f"{thr:g}"] = None if hit is None else {"s": hit[0], "steps": hit[1]}
+        out["methods"][name] = {"dt": dt, "momentum": mu,
+                                "curve": [[round(a, 4), b, d, f] for a, b, d, f in c],
+                                "time_to_F_per_sqrtN": reach}
+        print(f"[convergence] {name}: {c[-1][1]} steps in {c[-1][0]:.2f} s, "
+              f"E-Emin {c[-1][2]:.4g}, |F|/sqrtN {c[-1][3]:.3g}", file=sys.stderr, flush=True)
+    lat.close()
+    return out
+
+
+def step_scaling_leg(sizes=(16, 24, 32, 48, 64), seeds=(0, 1, 2), tol=1e-6, max_steps=200000):
+    """Steps FIRE needs to reach max|F| < tol from a random start, against the
+    box side L: periodic bulk, and one homeotropic colloid of radius L/4 at
+    the centre (the paper reports growth about like L and L^(3/2))."""
+    import numpy as np
+
+    from paper_1911_07045_amd import lqfire, synth
+
+    out = {"tol": tol, "max_steps": max_steps, "prec": "f64", "geometries": {}}
+    for geo in ("bulk", "colloid"):
+        rows = []
+        for L in sizes:
+            cfg = synth.bulk(L, prec="f64")
+            if geo == "colloid":
+                c = (L - 1) / 2.0
+                cfg["objects"] = [dict(kind="sphere", center=(c, c, c), radius=L / 4.0, law="rp", W=5.0,
+                                       dir="normal")]
+            steps = []
+            for sd in seeds:
+                lat = lqfire.lattice_from_config(cfg)
+                q = _random_start(lat, cfg, seed=1000 * L + sd)
+                rep = lat.minimize(lqfire.fire_params_from_config(cfg, force_tol=tol, max_steps=max_steps), q)[0]
+                steps.append(int(rep.step) if rep.status == lqfire.CONVERGED else None)
+                del q
+                lat.close()
+            ok = [s for s in steps if s is not None]
+            rows.append({"L": L, "steps": steps, "median": float(np.median(ok)) if ok else None})
+            print(f"[step-scaling] {geo} L={L}: {steps}", file=sys.stderr, flush=True)
+        pts = [(r["L"], r["median"]) for r in rows if r["median"]]
+        slope = None
+        if len(pts) >= 2:
+            x = np.log([p[0] for p in pts])
+            y = np.log([p[1] for p in pts])
+            slope = float(np.polyfit(x, y, 1)[0])
+        out["geometries"][geo] = {"rows": rows, "loglog_slope": slope}
+    return out
+
+
 def cpu_leg(cfg):
     """The FP64 oracle on the same workload: FIRE initialisation untimed,
     then whole FIRE steps over the full lattice until about 10 s have passed."""
@@ -404,6 +539,10 @@ def main():
                     help="print the hash of the kernel sources that a counter summary records")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of a known size (HBM counter scale)")
+    ap.add_argument("--convergence", action="store_true",
+                    help="only compare FIRE with tuned gradient descent and Nesterov on the 256^3 bulk box")
+    ap.add_argument("--step-scaling", action="store_true",
+                    help="only count FIRE steps to a force tolerance against the box side (bulk, one colloid)")
     args = ap.parse_args()
     if args.kernel_hash:
         print(kernel_source_hash())
@@ -427,6 +566,12 @@ def main():
         return
     if args.copy_ceiling:
         print(json.dumps({"copy_ceiling": copy_ceiling()}), flush=True)
+        return
+    if args.convergence:
+        print(json.dumps({"convergence": convergence_leg()}), flush=True)
+        return
+    if args.step_scaling:
+        print(json.dumps({"step_scaling": step_scaling_leg()}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs one GPU only: the hot path here is a single-GPU lattice "
