@@ -624,6 +624,12 @@ def main():
     if not args.no_precision and cfg["prec"] == "f32":
         print("[bench] precision form", file=sys.stderr, flush=True)
         out["precision"] = precision_leg(cfg)
+        if cfg["name"] == "multi_colloid256":
+            # the 128^3 colloid slab (walls, colloid, L2/L3) in both precisions
+            from paper_1911_07045_amd import synth
+
+            slab = synth.colloid_slab(128)
+            out["precision"]["colloid_slab128"] = precision_leg(slab)
     if not args.no_minimizers:
         print("[bench] gradient descent / Nesterov steps", file=sys.stderr, flush=True)
         out["minimizers"] = minimizer_leg(cfg)
