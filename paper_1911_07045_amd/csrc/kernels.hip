@@ -857,7 +857,9 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
         if (!BULK && W == 1) {
             const int f = j - 1;
             const bool bulk_plane = f >= 1 && f <= 64 && ((plane_bulk >> (f - 1)) & 1);
-            if (!bulk_plane) anch_load(L, (m_newer & M_ANCH) ? a_newer : 0, A);
+            // only waves with an anchored site issue the loads
+            if (!bulk_plane && __builtin_amdgcn_ballot_w64((m_newer & M_ANCH) != 0) != 0)
+                anch_load(L, (m_newer & M_ANCH) ? a_newer : 0, A);
         }
 #pragma unroll
         for (int c = 0; c < 5; ++c) { v1_older[c] = v1_newer[c]; q_older[c] = q_newer[c]; }
