@@ -96,6 +96,11 @@ CASES = {
     "wide_colloid_walls_L23": dict(shape=(70, 10, 14), periodic=(True, True, False), L2=1.16, L3=0.7, objects=[
         dict(kind="wall", axis=2, plane=0, law="nd", W=0.5, dir=(1.0, 0.0, 0.0)),
         dict(kind="sphere", center=(66.5, 4.0, 7.2), radius=3.6, law="rp", W=6.0, dir="normal")]),
+    "wide_chiral_walls_colloid_L234": dict(shape=(66, 9, 12), periodic=(True, True, False), L2=1.16, L3=0.7,
+                                           L4=-0.8, objects=[
+        dict(kind="wall", axis=2, plane=0, law="fg", W=0.7),
+        dict(kind="sphere", center=(40.2, 4.1, 6.3), radius=3.1, law="rp", W=4.0, dir="normal")],
+        fields=[((0.0, 0.6, 0.8), 1.2)]),
     "sandwiched_plane_L23": dict(shape=(66, 5, 3), L2=1.16, L3=0.3, objects=[
         dict(kind="wall", axis=2, plane=0, law="nd", W=0.7, dir=(0.0, 1.0, 0.0)),
         dict(kind="wall", axis=2, plane=2, law="nd", W=0.2, dir="normal")]),
@@ -126,7 +131,7 @@ def test_forces_and_energy_fp64(ora, name):
 @pytest.mark.parametrize("name", ["bulk32_L1", "ragged_periodic_L23", "colloid_slab24_L23",
                                   "patterned_records_L23", "fg_walls_sphere_field_L23",
                                   "chiral_L234_walls_colloid_open", "wide_spheres_wall_records_L1",
-                                  "wide_colloid_walls_L23"])
+                                  "wide_colloid_walls_L23", "wide_chiral_walls_colloid_L234"])
 def test_forces_and_energy_fp32(ora, name):
     c = dict(CASES[name])
     say(f"[forces f32] {name} {c['shape']}")
