@@ -216,6 +216,20 @@ def test_fire_trajectory_fg_sphere_field_L23(ora):
     _fire_trajectory(ora, p, lat, q0, 150, 10, 1e-10)
 
 
+def test_fire_trajectory_wide_tiles_anchoring(ora):
+    """FP64 FIRE on wide tiles (L1: 64 x 8, L2/L3/L4: 64 x 4) with anchored
+    sites inside otherwise bulk tiles, whose anchoring forms are loaded ahead
+    of the force: forces agree to 1e-10 over 100 steps."""
+    for name, seed in (("wide_spheres_wall_records_L1", 23), ("wide_chiral_walls_colloid_L234", 29)):
+        c = CASES[name]
+        say(f"[fire] {name} 100 steps")
+        p, lat = pair(ora, c["shape"], c.get("periodic", (True, True, True)), L2=c.get("L2", 0.0),
+                      L3=c.get("L3", 0.0), L4=c.get("L4", 0.0), objects=c["objects"],
+                      records=c.get("records", ()), fields=c.get("fields", ()))
+        q0 = p.uniaxial(synth.random_directors(seed, p.N))
+        _fire_trajectory(ora, p, lat, q0, 100, 10, 1e-10)
+
+
 def test_fire_trajectory_chiral_L4(ora):
     """The chiral L4 term with L2/L3, walls and a colloid on a box open in y:
     forces agree to 1e-10 over 150 FIRE steps."""
