@@ -237,9 +237,21 @@ int lq_fire_init(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, vo
  * hit a non-finite reduction. */
 int lq_fire_step(lq_lattice* lat, int64_t n_steps, lq_fire_report* out);
 
-/* lq_fire_init (fresh) + lq_fire_step until converged or max_steps. */
+/* Result of a whole minimization (Algorithm 1 run to its stop test): the
+ * final controller, the discrete energy of the final q (sec. III.B) and the
+ * per-site force norm |F| / sqrt(N_sim) that the paper plots (Fig. 2). */
+typedef struct {
+    lq_fire_report fire;     /* status LQ_CONVERGED / LQ_MAX_STEPS / LQ_NONFINITE, steps, max|F_i|, |F| */
+    lq_energy_terms energy;  /* energy terms of the final q, as lq_energy gives them */
+    double normF_per_site;   /* fire.normF / sqrt(energy.n_sim) */
+} lq_min_result;
+
+/* lq_fire_init (fresh) + lq_fire_step until converged or max_steps, then
+ * lq_energy of the final q.  out (host, may be NULL) receives the result;
+ * when the run stops on a non-finite reduction it returns LQ_ENONFINITE with
+ * out->fire filled and the energy terms set to NaN. */
 int lq_minimize(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F,
-                void* workspace, int64_t workspace_bytes, lq_fire_report* out);
+                void* workspace, int64_t workspace_bytes, lq_min_result* out);
 
 /* ---- gradient descent and Nesterov's accelerated gradient ----
  * The alternatives to FIRE that sec. III.B names (steepest descent, and
@@ -272,9 +284,10 @@ typedef struct {
 int lq_descent_init(lq_lattice* lat, const lq_descent_params* dp, void* q, void* v, void* F,
                     void* workspace, int64_t workspace_bytes, const lq_fire_report* resume);
 
-/* lq_descent_init (fresh) + lq_fire_step until converged or max_steps. */
+/* lq_descent_init (fresh) + lq_fire_step until converged or max_steps, then
+ * lq_energy of the final q; out as for lq_minimize. */
 int lq_descent_minimize(lq_lattice* lat, const lq_descent_params* dp, void* q, void* v, void* F,
-                        void* workspace, int64_t workspace_bytes, lq_fire_report* out);
+                        void* workspace, int64_t workspace_bytes, lq_min_result* out);
 
 /* ---- batched FIRE for many small lattices (continuous batching) ----
  * A batch advances all its member lattices by one FIRE step per kernel

@@ -88,8 +88,6 @@ def lib():
         L.ora_forces.argtypes = [C.POINTER(_Problem), dp, dp]
         L.ora_forces_at.restype = None
         L.ora_forces_at.argtypes = [C.POINTER(_Problem), dp, C.c_int64, C.POINTER(C.c_int64), dp]
-        L.ora_site_energy.restype = C.c_double
-        L.ora_site_energy.argtypes = [C.POINTER(_Problem), dp, C.c_int64]
         L.ora_fire_init.restype = None
         L.ora_fire_init.argtypes = [C.POINTER(FireParams), C.POINTER(FireState), C.c_int64, dp, dp,
                                     dp, FORCE_FN, C.c_void_p, C.c_int]
@@ -231,10 +229,6 @@ class Problem:
         lib().ora_forces_at(C.byref(self._s), _dp(q), len(sites),
                             sites.ctypes.data_as(C.POINTER(C.c_int64)), _dp(out))
         return out
-
-    def site_energy(self, q, s):
-        q = self._chk(q)
-        return lib().ora_site_energy(C.byref(self._s), _dp(q), int(s))
 
     # ---- FIRE (Algorithm 1) ----
     def fire_init(self, params, q, v=None, keep_v=False):

@@ -732,16 +732,6 @@ int64_t ora_descent_steps_lattice(const ora_problem *p, const ora_descent_params
     return ora_descent_steps(dp, st, 5 * nsites(p), q, m, F, lattice_force, (void *)p, n_steps, trace);
 }
 
-/* ---- per-site energy density, for sampled checks on large lattices:
- *      f_bulk + averaged f_dist of one simulated site (anchoring excluded) */
-double ora_site_energy(const ora_problem *p, const double *q, int64_t s)
-{
-    if (!simulated(p, s)) return 0.0;
-    double Q[3][3];
-    load_Q(p, q, s, Q);
-    return f_bulk(p, Q) + f_ext(p, Q) + e_dist_site(p, q, s);
-}
-
 /* ---- force at a list of sites only (for sampled checks on lattices too
  *      large for a full pass); out is [n_sites][5]; anchoring included ---- */
 void ora_forces_at(const ora_problem *p, const double *q, int64_t n_sites, const int64_t *sites,

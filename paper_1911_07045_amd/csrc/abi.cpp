@@ -667,36 +667,43 @@ int lq_fire_step(lq_lattice* lat, int64_t n_steps, lq_fire_report* out) {
     return LQ_OK;
 }
 
-int lq_minimize(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F, void* workspace,
-                int64_t workspace_bytes, lq_fire_report* out) {
-    int rc = lq_fire_init(lat, fp, q, v, F, workspace, workspace_bytes, nullptr);
-    if (rc != LQ_OK) return rc;
+// Steps the bound minimizer until it stops (chunks of growing length, so a
+// run that converges early is not stepped far past its stop), then
+// evaluates the energy of the final state.
+static int run_to_stop(lq_lattice* lat, int64_t max_steps, lq_min_result* out) {
     lq_fire_report r{};
     fill_report(*lat->h_state, &r);
+    int rc = LQ_OK;
     int64_t chunk = 64;
     while (r.status == LQ_RUNNING) {
-        rc = lq_fire_step(lat, std::min<int64_t>(chunk, fp->max_steps - r.step), &r);
+        rc = lq_fire_step(lat, std::min<int64_t>(chunk, max_steps - r.step), &r);
         if (rc != LQ_OK) break;
         chunk = std::min<int64_t>(chunk * 2, 1024);
     }
-    if (out) *out = r;
+    lq_energy_terms e{};
+    e.bulk = e.elastic = e.anchoring = e.external = e.total = NAN;
+    e.n_sim = lat->n_sim;
+    if (rc == LQ_OK) rc = lq_energy(lat, lat->q, &e);
+    if (out) {
+        out->fire = r;
+        out->energy = e;
+        out->normF_per_site = lat->n_sim > 0 ? r.normF / std::sqrt((double)lat->n_sim) : 0.0;
+    }
     return rc;
 }
 
+int lq_minimize(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F, void* workspace,
+                int64_t workspace_bytes, lq_min_result* out) {
+    int rc = lq_fire_init(lat, fp, q, v, F, workspace, workspace_bytes, nullptr);
+    if (rc != LQ_OK) return rc;
+    return run_to_stop(lat, fp->max_steps, out);
+}
+
 int lq_descent_minimize(lq_lattice* lat, const lq_descent_params* dp, void* q, void* v, void* F, void* workspace,
-                        int64_t workspace_bytes, lq_fire_report* out) {
+                        int64_t workspace_bytes, lq_min_result* out) {
     int rc = lq_descent_init(lat, dp, q, v, F, workspace, workspace_bytes, nullptr);
     if (rc != LQ_OK) return rc;
-    lq_fire_report r{};
-    fill_report(*lat->h_state, &r);
-    int64_t chunk = 64;
-    while (r.status == LQ_RUNNING) {
-        rc = lq_fire_step(lat, std::min<int64_t>(chunk, dp->max_steps - r.step), &r);
-        if (rc != LQ_OK) break;
-        chunk = std::min<int64_t>(chunk * 2, 1024);
-    }
-    if (out) *out = r;
-    return rc;
+    return run_to_stop(lat, dp->max_steps, out);
 }
 
 const char* lq_last_error(const lq_lattice* lat) { return lat ? lat->err.c_str() : g_err.c_str(); }

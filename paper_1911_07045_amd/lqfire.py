@@ -74,6 +74,22 @@ class FireReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class MinResult(C.Structure):
+    """lq_min_result: the final controller, the energy of the final q and
+    |F| / sqrt(N_sim).  Attributes of the controller (status, step, maxF, ...)
+    read through to `fire`."""
+    _fields_ = [("fire", FireReport), ("energy", EnergyTerms), ("normF_per_site", C.c_double)]
+
+    def __getattr__(self, name):
+        return getattr(self.fire, name)
+
+    def as_dict(self):
+        d = self.fire.as_dict()
+        d.update({k: getattr(self.energy, k) for k, _ in EnergyTerms._fields_})
+        d["normF_per_site"] = self.normF_per_site
+        return d
+
+
 class DescentParams(C.Structure):
     _fields_ = [("method", C.c_int32), ("pad", C.c_int32), ("dt", C.c_double),
                 ("momentum", C.c_double), ("force_tol", C.c_double), ("max_steps", C.c_int64)]
@@ -109,11 +125,11 @@ def lib():
                                        C.POINTER(FireReport)]),
             "lq_fire_step": (C.c_int, [vp, i64, C.POINTER(FireReport)]),
             "lq_minimize": (C.c_int, [vp, C.POINTER(FireParams), vp, vp, vp, vp, i64,
-                                      C.POINTER(FireReport)]),
+                                      C.POINTER(MinResult)]),
             "lq_descent_init": (C.c_int, [vp, C.POINTER(DescentParams), vp, vp, vp, vp, i64,
                                           C.POINTER(FireReport)]),
             "lq_descent_minimize": (C.c_int, [vp, C.POINTER(DescentParams), vp, vp, vp, vp, i64,
-                                              C.POINTER(FireReport)]),
+                                              C.POINTER(MinResult)]),
             "lq_director_field": (C.c_int, [vp, vp, vp, vp, vp, C.c_double, C.POINTER(C.c_int64)]),
             "lq_last_error": (C.c_char_p, [vp]),
             "lq_batch_create": (C.c_int, [i32, vp, C.POINTER(vp)]),
@@ -364,10 +380,11 @@ class Lattice:
         return r
 
     def minimize(self, params, q, v=None, F=None):
+        """lq_minimize: returns (MinResult, q, v, F)."""
         v = self.empty() if v is None else v
         F = self.empty() if F is None else F
         ws, off = self.workspace()
-        r = FireReport()
+        r = MinResult()
         _check(lib().lq_minimize(self.h, C.byref(params), self._field(q, "q"), self._field(v, "v"),
                                  self._field(F, "F"), C.c_void_p(ws.data_ptr() + off),
                                  ws.numel() - off, C.byref(r)), self.h)
@@ -387,7 +404,7 @@ class Lattice:
         v = self.zeros() if v is None else v
         F = self.empty() if F is None else F
         ws, off = self.workspace()
-        r = FireReport()
+        r = MinResult()
         _check(lib().lq_descent_minimize(self.h, C.byref(params), self._field(q, "q"), self._field(v, "v"),
                                          self._field(F, "F"), C.c_void_p(ws.data_ptr() + off),
                                          ws.numel() - off, C.byref(r)), self.h)
@@ -442,43 +459,6 @@ class Batch:
         if rc not in (LQ_OK, LQ_ENONFINITE):
             _check(rc)
         return [reps[i] for i in range(n)]
-
-
-# ---- the ABI names, as plain functions ----
-def lattice_create(shape, **kw) -> Lattice:
-    return Lattice(shape, **kw)
-
-
-def set_boundaries(lat: Lattice, objects=(), site_records=(), object_sites=()):
-    lat.set_boundaries(objects, site_records, object_sites)
-
-
-def set_field(lat: Lattice, fields=()):
-    lat.set_field(fields)
-
-
-def compute_forces(lat: Lattice, q, F=None):
-    return lat.compute_forces(q, F)
-
-
-def energy(lat: Lattice, q):
-    return lat.energy(q)
-
-
-def fire_step(lat: Lattice, n_steps):
-    return lat.fire_step(n_steps)
-
-
-def minimize(lat: Lattice, params, q, v=None, F=None):
-    return lat.minimize(params, q, v, F)
-
-
-def director_field(lat: Lattice, q, threshold):
-    return lat.director_field(q, threshold)
-
-
-def descent_minimize(lat: Lattice, params, q, v=None, F=None):
-    return lat.descent_minimize(params, q, v, F)
 
 
 def lattice_from_config(cfg, prec=None, **kw) -> Lattice:

@@ -151,6 +151,51 @@ def test_forces_are_the_exact_gradient(ora, name):
     assert np.all(F[:, obj] == 0.0)
 
 
+def _forces_at_cases(ora):
+    """Every geometry whose full force field is pinned to the exact gradient
+    above, plus degenerate planar walls with fields, per-site records, the
+    chiral term on an open box, and a 24^3 colloid slab (walls, sphere,
+    L2/L3)."""
+    for name in sorted(GEOMETRIES):
+        g = dict(GEOMETRIES[name])
+        shape = g.pop("shape")
+        yield name, ora.Problem(shape, A=A, B=B, C_=C, L1=2.32, **g)
+    yield "fg_walls_sphere_fields", ora.Problem(
+        (4, 3, 5), L1=2.32, L2=0.9, L3=0.4, fields=[((0.2, 0.5, -1.0), 0.7)], objects=[
+            dict(kind="wall", axis=2, plane=0, law="fg", W=0.8),
+            dict(kind="wall", axis=2, plane=4, law="rp", W=-3.0),
+            dict(kind="sphere", center=(1.7, 1.2, 2.0), radius=1.1, law="rp", W=-2.0)])
+    yield "fg_records", ora.Problem(
+        (3, 4, 3), L1=2.32, fields=[((1.0, 0.0, 0.0), -0.5)],
+        site_records=[dict(site=7, law="fg", W=1.3, nu=(0.2, 0.9, 0.3)),
+                      dict(site=7, law="nd", W=0.4, n0=(1, 0, 0)),
+                      dict(site=20, law="rp", W=-5.0, nu=(0, 0, 1))])
+    yield "L4_open", ora.Problem(
+        (4, 3, 5), (False, True, False), L1=2.32, L2=0.9, L3=0.4, L4=-0.7, objects=[
+            dict(kind="sphere", center=(1.5, 1.0, 2.0), radius=0.9, law="nd", W=0.6, dir="normal")],
+        fields=[((0.1, 0.2, 0.3), 0.5)])
+    cfg = synth.colloid_slab(24)
+    cfg["objects"][2]["radius"] = 5.0
+    yield "colloid_slab24", ora.Problem(cfg["shape"], cfg["periodic"], L1=cfg["L1"], L2=cfg["L2"],
+                                        L3=cfg["L3"], objects=cfg["objects"])
+
+
+def test_forces_at_sites_equal_the_full_force_field(ora):
+    """The site-list force (used for sampled checks of lattices too large for
+    a full pass) is the same gradient of the discrete energy (sec. III.B) as
+    the full force field, which the tests above pin to the exact derivative:
+    it agrees at every site of every case, up to the summation order of the
+    anchoring terms."""
+    for i, (name, p) in enumerate(_forces_at_cases(ora)):
+        q = rand_q(p, seed=100 + i)
+        F = p.forces(q).reshape(5, -1).T
+        sites = np.arange(p.N)[::-1].copy()  # every site, in an order unlike the full pass
+        Fa = p.forces_at(q, sites)
+        assert np.abs(Fa - F[sites]).max() <= 1e-15 * np.abs(F).max(), name
+        obj = p.types[sites] == 2
+        assert np.all(Fa[obj] == 0.0), name
+
+
 def test_translation_invariance(ora):
     """Rolling q by a lattice vector on a periodic box rolls F and keeps E."""
     p = ora.Problem((5, 6, 7), L1=2.32, L2=1.16, L3=0.4)
