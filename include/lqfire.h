@@ -253,6 +253,25 @@ typedef struct {
 int lq_minimize(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F,
                 void* workspace, int64_t workspace_bytes, lq_min_result* out);
 
+/* ---- allocation-free minimization ----
+ * For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lq_minimize
+ * without the workspace argument.  The workspace (second q, v, F, partial
+ * sums, device FIRE state) lives in a fixed array of
+ * LQ_NOALLOC_WORKSPACE_BYTES that the library holds on each GPU it runs on
+ * until the process ends; the call allocates nothing (no hipMalloc, hipFree
+ * or allocating library routine).  q, v, F are the caller's buffers as for
+ * lq_minimize, with the same result and the same trajectory bit for bit.
+ * LQ_ENOMEM, before any device work, when lq_workspace_bytes(lat) exceeds
+ * LQ_NOALLOC_WORKSPACE_BYTES (64^3 sites fit in FP64, 80^3 in FP32).  Every
+ * call on one GPU shares that GPU's array, and it keeps the last call's
+ * contents: calls that overlap on one GPU (two host threads, or two streams)
+ * race and give undefined results.  The lattice is left unbound on return
+ * (lq_fire_step gives LQ_ESTATE), since the next call may reuse the array. */
+#define LQ_NOALLOC_WORKSPACE_BYTES ((int64_t)32 << 20)
+int lq_minimize_noalloc(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F,
+                        lq_min_result* out);
+
 /* ---- gradient descent and Nesterov's accelerated gradient ----
  * The alternatives to FIRE that sec. III.B names (steepest descent, and
  * Nesterov's momentum method of the GUI).  The paper gives no formulas; the

@@ -19,6 +19,7 @@ DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-pa
           "-ffp-contract=on"]
 SOURCES = [
     ("kernels.hip", DEVICE),
+    ("noalloc.hip", DEVICE),
     ("abi.cpp", []),
     ("geometry.cpp", ["-ffp-contract=off"]),
 ]
@@ -35,7 +36,7 @@ def _compile(src, extra):
 
 def build() -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=3) as ex:
+    with cf.ThreadPoolExecutor(max_workers=5) as ex:
         objs = list(ex.map(lambda s: _compile(*s), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs

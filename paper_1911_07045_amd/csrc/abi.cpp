@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "lq_aux.h"
 #include "lq_internal.h"
 
 using namespace lq;
@@ -704,6 +705,30 @@ int lq_descent_minimize(lq_lattice* lat, const lq_descent_params* dp, void* q, v
     int rc = lq_descent_init(lat, dp, q, v, F, workspace, workspace_bytes, nullptr);
     if (rc != LQ_OK) return rc;
     return run_to_stop(lat, dp->max_steps, out);
+}
+
+int lq_minimize_noalloc(lq_lattice* lat, const lq_fire_params* fp, void* q, void* v, void* F,
+                        lq_min_result* out) {
+    if (!lat) return fail(nullptr, LQ_EINVAL, "lattice is NULL");
+    lat->bound = false;
+    const int64_t need = lq_workspace_bytes(lat);
+    if (need > LQ_NOALLOC_WORKSPACE_BYTES) {
+        char msg[192];
+        std::snprintf(msg, sizeof msg,
+                      "lattice needs %lld bytes of FIRE workspace; lq_minimize_noalloc holds at most %lld "
+                      "(use lq_minimize with a caller-allocated workspace)",
+                      (long long)need, (long long)LQ_NOALLOC_WORKSPACE_BYTES);
+        return fail(lat, LQ_ENOMEM, msg);
+    }
+    HIPCHK(lat, hipSetDevice(lat->device));
+    void* ws = nullptr;
+    int rc = noalloc_workspace(lat->device, &ws);
+    if (rc != LQ_OK) return fail(lat, rc, "device address of the fixed workspace not available");
+    rc = lq_fire_init(lat, fp, q, v, F, ws, LQ_NOALLOC_WORKSPACE_BYTES, nullptr);
+    if (rc == LQ_OK) rc = run_to_stop(lat, fp->max_steps, out);
+    // the next call on this GPU may reuse the array: nothing may continue from it
+    lat->bound = false;
+    return rc;
 }
 
 const char* lq_last_error(const lq_lattice* lat) { return lat ? lat->err.c_str() : g_err.c_str(); }

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "liblqfire.so")
 
 LQ_OK, LQ_EINVAL, LQ_EUNSUPPORTED, LQ_ENOMEM, LQ_EHIP, LQ_ENONFINITE, LQ_ESTATE = 0, -1, -2, -3, -4, -5, -6
 LQ_F64, LQ_F32 = 0, 1
+# bytes of the fixed per-GPU workspace of lq_minimize_noalloc (LQ_NOALLOC_WORKSPACE_BYTES)
+NOALLOC_WORKSPACE_BYTES = 32 << 20
 LQ_OBJ_WALL, LQ_OBJ_SPHERE, LQ_OBJ_PATTERNED_WALL = 1, 2, 3
 LQ_LAW_ND, LQ_LAW_RP, LQ_LAW_FG = 0, 1, 2
 LAWS = {"nd": LQ_LAW_ND, "rp": LQ_LAW_RP, "fg": LQ_LAW_FG}
@@ -126,6 +128,7 @@ def lib():
             "lq_fire_step": (C.c_int, [vp, i64, C.POINTER(FireReport)]),
             "lq_minimize": (C.c_int, [vp, C.POINTER(FireParams), vp, vp, vp, vp, i64,
                                       C.POINTER(MinResult)]),
+            "lq_minimize_noalloc": (C.c_int, [vp, C.POINTER(FireParams), vp, vp, vp, C.POINTER(MinResult)]),
             "lq_descent_init": (C.c_int, [vp, C.POINTER(DescentParams), vp, vp, vp, vp, i64,
                                           C.POINTER(FireReport)]),
             "lq_descent_minimize": (C.c_int, [vp, C.POINTER(DescentParams), vp, vp, vp, vp, i64,
@@ -390,6 +393,16 @@ class Lattice:
                                  ws.numel() - off, C.byref(r)), self.h)
         self._bound = (q, v, F)
         return r, q, v, F
+
+    def minimize_noalloc(self, params, q, v, F):
+        """lq_minimize_noalloc: lq_minimize with the library's fixed workspace;
+        q, v, F are the caller's (nothing is allocated).  Returns MinResult;
+        the lattice is left unbound."""
+        r = MinResult()
+        _check(lib().lq_minimize_noalloc(self.h, C.byref(params), self._field(q, "q"), self._field(v, "v"),
+                                         self._field(F, "F"), C.byref(r)), self.h)
+        self._bound = None
+        return r
 
     def descent_init(self, params, q, v, F, resume=None):
         """Binds a gradient-descent or Nesterov run (lq_descent_init); advance it with fire_step."""

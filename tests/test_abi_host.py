@@ -29,6 +29,14 @@ def test_library_exports_every_declared_function():
     L = lqfire.lib()
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
+    assert "lq_minimize_noalloc" in names
+
+
+def test_noalloc_workspace_size_matches_header():
+    txt = open(os.path.join(ROOT, "include", "lqfire.h")).read()
+    m = re.search(r"#define LQ_NOALLOC_WORKSPACE_BYTES \(\(int64_t\)(\d+) << (\d+)\)", txt)
+    assert m, "LQ_NOALLOC_WORKSPACE_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == lqfire.NOALLOC_WORKSPACE_BYTES
 
 
 def _zero_strength(objs, recs):
