@@ -371,6 +371,132 @@ def oracle_timing(plan=(("bulk32", 50, 10), ("colloid_slab128", 3, 0), ("multi_c
     return rows
 
 
+GOLDEN_SLAB = os.path.join(ROOT, "tests", "golden", "colloid_slab128_fire.json")
+
+
+def _stage_vs_oracle(gold, lat, q, rep, sites):
+    """Errors of one stage's GPU result against the oracle's stored one:
+    energy terms (relative to each term), max|F_i| and |F|/sqrt(N_sim)
+    (relative), max|dQ| over the stored sites, and whether the controller
+    took the same decisions (step, n_pos, restarts)."""
+    import numpy as np
+
+    e = lat.energy(q)
+    ge = gold["energy"]
+    qs = q.double().reshape(5, -1)[:, sites].T.cpu().numpy()
+    n_sim = e["n_sim"]
+    gs = gold["state"]
+    return {
+        "rel_energy_err": {k: abs(e[k] - ge[k]) / max(abs(ge[k]), 1e-300)
+                           for k in ("bulk", "elastic", "anchoring", "total")},
+        "rel_maxF_err": abs(rep.maxF - gold["maxF"]) / gold["maxF"],
+        "rel_normF_per_site_err": abs(rep.normF / n_sim ** 0.5 - gold["normF_over_sqrt_nsim"])
+                                  / gold["normF_over_sqrt_nsim"],
+        "max_abs_dQ_sampled": float(np.abs(qs - np.array(gold["q"])).max()),
+        "controller_equal": (rep.step, rep.n_pos, rep.restarts) == (gs["step"], gs["n_pos"], gs["restarts"]),
+    }
+
+
+def precision_vs_oracle(golden=GOLDEN_SLAB):
+    """The 128^3 colloid slab (walls, colloid, L2/L3) on the oracle's stored
+    FP64 schedule: 2000 FIRE steps from the workload's random start, then a
+    fresh FIRE start (v = 0, dt0) for 200 FP64 steps.  Run on the GPU in FP64
+    and in the FP32 form (FP32 state and FP64 reductions for the 2000 steps,
+    then the 200-step FP64 polish), each stage compared with the oracle's
+    stored energy terms, forces and q at its sampled sites."""
+    import numpy as np
+    import torch
+
+    from paper_1911_07045_amd import lqfire, synth
+
+    if not os.path.exists(golden):
+        return {"status": f"no stored oracle result ({os.path.relpath(golden, ROOT)} missing)"}
+    with open(golden) as f:
+        g = json.load(f)
+    cfg = synth.colloid_slab(128)
+    sites = np.array(g["sites"], dtype=np.int64)
+    steps = dict((st["stage"], st["steps"]) for st in g["schedule"])
+    t0 = time.perf_counter()
+    lat64 = lqfire.lattice_from_config(cfg, prec="f64")
+    dirs = torch.from_numpy(np.ascontiguousarray(synth.random_directors(cfg["dir_seed"], lat64.N))).cuda()
+
+    def fire(lat, q, n):
+        v, F = lat.empty(), lat.empty()
+        lat.fire_init(lqfire.fire_params_from_config(cfg, force_tol=0.0, max_steps=n), q, v, F)
+        return lat.fire_step(n)
+
+    out = {"workload": "colloid_slab128", "reference": "FP64 oracle, stored in " + os.path.relpath(golden, ROOT),
+           "schedule": f"{steps['fire2000']} FIRE steps from random directors (seed {cfg['dir_seed']}), then "
+                       f"{steps['polish200']} FP64 FIRE steps from a fresh start",
+           "sampled_sites": len(sites), "oracle_seconds": g.get("seconds")}
+    for form in ("f64", "f32"):
+        lat = lat64 if form == "f64" else lqfire.lattice_from_config(cfg, prec="f32")
+        q = lat.set_uniaxial(dirs, lat.empty())
+        rep = fire(lat, q, steps["fire2000"])
+        r = {"fire2000": _stage_vs_oracle(g["stages"]["fire2000"], lat, q, rep, sites)}
+        q64 = q if form == "f64" else q.double().contiguous()
+        if form == "f32":
+            del q
+            lat.close()
+        rep = fire(lat64, q64, steps["polish200"])
+        r["polish200"] = _stage_vs_oracle(g["stages"]["polish200"], lat64, q64, rep, sites)
+        out["fp64_gpu" if form == "f64" else "fp32_form"] = r
+        del q64
+    lat64.close()
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
+def precision_minima(n=128, tol=1e-9, fp32_tol=1e-5, max_steps=400000, chunk=5000):
+    """Converged minima of the two forms on the colloid slab, from a uniform
+    x-aligned director (a smooth relaxation into one minimum): FP64 FIRE to
+    max|F_i| < tol; the FP32 form (FP32 FIRE to max|F_i| < fp32_tol, above
+    its rounding floor, then an FP64 polish from a fresh FIRE start to tol).
+    Reports the relative energy difference and max|dQ| over every site,
+    against the bars 1e-6 and 1e-5."""
+    import torch
+
+    from paper_1911_07045_amd import lqfire, synth
+
+    cfg = synth.colloid_slab(n)
+    t0 = time.perf_counter()
+    lat64 = lqfire.lattice_from_config(cfg, prec="f64")
+    lat32 = lqfire.lattice_from_config(cfg, prec="f32")
+    N = lat64.N
+    dirs = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    dirs[:N] = 1.0
+
+    def run(lat, q, force_tol, label):
+        v, F = lat.empty(), lat.empty()
+        lat.fire_init(lqfire.fire_params_from_config(cfg, force_tol=force_tol, max_steps=max_steps), q, v, F)
+        rep = lat.fire_step(0)
+        while rep.status == lqfire.RUNNING:
+            rep = lat.fire_step(chunk)
+            print(f"[precision-minima] {label}: step {rep.step} maxF {rep.maxF:.3e}", file=sys.stderr, flush=True)
+        return rep
+
+    q64 = lat64.set_uniaxial(dirs, lat64.empty())
+    r64 = run(lat64, q64, tol, "fp64")
+    q32 = lat32.set_uniaxial(dirs, lat32.empty())
+    r32 = run(lat32, q32, fp32_tol, "fp32")
+    qp = q32.double().contiguous()
+    del q32
+    lat32.close()
+    rp = run(lat64, qp, tol, "fp32 + fp64 polish")
+    e64, ep = lat64.energy(q64)["total"], lat64.energy(qp)["total"]
+    dq = (qp - q64).abs().max().item()
+    de = abs(ep - e64) / abs(e64)
+    lat64.close()
+    return {"workload": f"colloid_slab{n}", "start": "uniform director along x, S = S0",
+            "fp64": {"steps": r64.step, "status": int(r64.status), "maxF": r64.maxF, "energy": e64},
+            "fp32_form": {"fp32_steps": r32.step, "fp32_status": int(r32.status), "fp32_maxF": r32.maxF,
+                          "polish_steps": rp.step, "status": int(rp.status), "maxF": rp.maxF, "energy": ep},
+            "both_converged": r64.status == lqfire.CONVERGED and rp.status == lqfire.CONVERGED,
+            "rel_energy_err": de, "max_abs_dQ": dq,
+            "pass_energy_1e-6": de <= 1e-6, "pass_dQ_1e-5": dq < 1e-5,
+            "seconds": time.perf_counter() - t0}
+
+
 def precision_leg(cfg, steps=2000, polish=200):
     """The FP32 form against the FP64 path on the same schedule: `steps` FIRE
     steps, then a fresh FIRE start (v = 0, dt0) for `polish` steps in FP64.
@@ -379,12 +505,23 @@ def precision_leg(cfg, steps=2000, polish=200):
     difference.  Two starts: a uniform director (a smooth relaxation, where
     the difference measures rounding) and the workload's random directors
     (a coarsening defect tangle, where small differences grow and the two
-    runs part ways).  The FP64 GPU path stands in for the oracle at this size
-    (it matches the oracle's per-step forces to 1e-10)."""
+    runs part ways).  The FP64 GPU path stands in for the oracle on the
+    whole schedule (the oracle needs seconds per step at this size; the GPU
+    path matches its per-step forces to 1e-10 on smaller boxes); at the end
+    of each FP64 run the oracle evaluates the force of the reference state
+    at sampled sites, which pins the reference at full size."""
     import numpy as np
     import torch
 
+    import oracle
     from paper_1911_07045_amd import lqfire, synth
+
+    p = oracle.Problem(cfg["shape"], cfg["periodic"], L1=cfg["L1"], L2=cfg["L2"], L3=cfg["L3"],
+                       objects=cfg["objects"])
+    rng = np.random.default_rng(20191115)
+    bnd = np.flatnonzero(p.types.reshape(-1) == 1)
+    sites = np.unique(np.concatenate([rng.choice(p.N, 1000, replace=False),
+                                      rng.choice(bnd, min(1000, len(bnd)), replace=False)]))
 
     nx, ny, nz = cfg["shape"]
     N = nx * ny * nz
@@ -416,7 +553,13 @@ def precision_leg(cfg, steps=2000, polish=200):
         rp = fire(lat64, qp, polish)
         rr = fire(lat64, q64, polish)
         ep, er = lat64.energy(qp)["total"], lat64.energy(q64)["total"]
-        out[start] = {"max_abs_dQ_before_polish": d1, "rel_energy_err_before_polish": e1,
+        F64 = lat64.compute_forces(q64)
+        Fo = p.forces_at(q64.cpu().numpy().reshape(p.field_shape), sites)
+        Fg = F64.reshape(5, -1)[:, sites].T.cpu().numpy()
+        ref_err = float(np.abs(Fg - Fo).max() / np.abs(Fo).max())
+        del F64
+        out[start] = {"reference_force_vs_oracle": {"sites": len(sites), "max_rel_err": ref_err},
+                      "max_abs_dQ_before_polish": d1, "rel_energy_err_before_polish": e1,
                       "max_abs_dQ_polished": (qp - q64).abs().max().item(),
                       "rel_energy_err_polished": abs(ep - er) / abs(er),
                       "maxF_polished": rp.maxF, "maxF_fp64": rr.maxF, "energy_fp64": er}
@@ -434,11 +577,15 @@ def serving_leg(n_requests=512, rate=20.0):
     from paper_1911_07045_amd import serve, synth
 
     reqs = synth.serving_stream(n_requests=n_requests, rate=rate)
-    srv = serve.Server(max_members=64, chunk=50)
+    srv = serve.Server(max_members=64, chunk=50, polish_steps=2000, fp32_floor=1e-4)
     results = srv.run(reqs, realtime=True)
     out = serve.summarize(results, srv.wall_s, srv.busy_s)
+    # a solve is a request that reached its force tolerance
+    out["solves_per_s"] = out["converged"].get("per_s", 0.0)
     out.update({"stream": f"{n_requests} requests, Poisson {rate}/s, side log-U[16,64], one colloid, "
-                          f"W_RP log-U[0.1,10], FP32, tol 1e-5 or 5000 steps",
+                          f"W_RP log-U[0.1,10], tol 1e-5: FP32 with FP64 reductions to max|F| < "
+                          f"{srv.fp32_floor:g} (the FP32 floor) or 5000 steps, then an FP64 polish "
+                          f"from the FP32 minimum to 1e-5, at most {srv.polish_steps} steps",
                 "max_members": 64, "chunk_steps": 50,
                 "hbm_budget_GB": srv.budget / 1e9})
     torch.cuda.synchronize()
@@ -446,7 +593,14 @@ def serving_leg(n_requests=512, rate=20.0):
 
 
 COPY_BYTES = 1 << 30
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_fire_f32_multi_colloid256_hbm.txt")
+
+
+def traffic_file(workload_name, dtype):
+    """The committed counter summary of the step kernel on one workload."""
+    return os.path.join(ROOT, "profiles", f"k_march_fire_{dtype}_{workload_name}_hbm.txt")
+
+
+TRAFFIC_FILE = traffic_file("multi_colloid256", "f32")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1911_07045_amd", "csrc", f) for f in ("kernels.hip", "lq_internal.h")]
 
 
@@ -466,19 +620,26 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload_name):
-    """HBM bytes per step-kernel launch from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or None when
-    the summary is for another workload or the kernel source has changed
-    since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
+def read_summary(path):
+    """key: value lines of a committed profile summary."""
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line:
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
+    return vals
+
+
+def measured_traffic(workload_name, dtype="f32"):
+    """HBM bytes per step-kernel launch from the committed counter summary
+    of this workload and state type (FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy's reading), or None when there is none or the kernel source
+    has changed since the counters were taken."""
+    path = traffic_file(workload_name, dtype)
+    if not os.path.exists(path):
+        return None
+    vals = read_summary(path)
     if vals.get("workload") != workload_name or vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
@@ -488,44 +649,93 @@ def measured_traffic(workload_name):
 
 
 def copy_calibration(reps=5):
-    """Plain device-to-device copies of COPY_BYTES each.  Under rocprofv3
-    --pmc FETCH_SIZE (or WRITE_SIZE) the per-dispatch counter of these copies,
-    against the known COPY_BYTES read and written, gives the factor that turns
-    the counter into HBM bytes."""
+    """Plain device copies of COPY_BYTES each (the library's streaming copy,
+    16 bytes per lane).  Under rocprofv3 --pmc FETCH_SIZE (or WRITE_SIZE) the
+    per-dispatch counter of these copies, against the known COPY_BYTES read
+    and written, gives the factor that turns the counter into HBM bytes."""
     import torch
+
+    from paper_1911_07045_amd import lqfire
+
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(reps):
-        dst.copy_(src)
+        lqfire.stream_copy([src], [dst], width=16)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "reps": reps}),
-          flush=True)
+    assert torch.equal(src, dst)
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "reps": reps,
+                      "kernel": "k_stream_copy<16>"}), flush=True)
 
 
-def copy_ceiling(n=256, fields=15, iters=40):
-    """Streaming ceiling for the step's access pattern: device copies of 15
-    SoA fields of n^3 FP32 values (in -> out), the same 2 x 15 streams a FIRE
-    step reads and writes, timed with HIP events.  Returns TB/s counting read
+def copy_ceiling(n=256, fields=15, iters=40, prec="f32"):
+    """Streaming ceiling for the step's access pattern: the library's
+    hand-written copy kernel (lq_stream_copy) over 15 SoA fields of n^3
+    values (in -> out), the same 2 x 15 streams a FIRE step reads and writes,
+    with the step kernel's non-temporal stores, timed with HIP events.  Two
+    widths: 16 bytes per lane per access (the streaming ceiling) and 4 bytes
+    (one FP32 value per lane, as the step kernel loads).  TB/s count read
     plus written bytes."""
     import torch
 
+    from paper_1911_07045_amd import lqfire
+
     N = n ** 3
-    src = [torch.zeros(N, dtype=torch.float32, device="cuda") for _ in range(fields)]
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    src = [torch.full((N,), float(i + 1), dtype=dtype, device="cuda") for i in range(fields)]
     dst = [torch.empty_like(x) for x in src]
-    for _ in range(3):
-        for a, b in zip(dst, src):
-            a.copy_(b)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(iters):
-        for a, b in zip(dst, src):
-            a.copy_(b)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / iters
-    tbs = 2.0 * fields * 4 * N / (ms * 1e-3) / 1e12
-    return {"fields": fields, "sites": N, "ms_per_pass": ms, "TB_per_s": tbs, "frac_hbm_peak": tbs * 1e3 / HBM_PEAK_GBS}
+    nbytes = 2.0 * fields * src[0].element_size() * N
+    out = {"kernel": "k_stream_copy", "fields": fields, "sites": N, "dtype": prec,
+           "store_policy": "non-temporal, as the step kernel's stores"}
+    for width in (16, 4):
+        for _ in range(3):
+            lqfire.stream_copy(src, dst, width=width)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(src, dst))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(iters):
+            lqfire.stream_copy(src, dst, width=width)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / iters
+        tbs = nbytes / (ms * 1e-3) / 1e12
+        out[f"width{width}"] = {"ms_per_pass": ms, "TB_per_s": tbs, "frac_hbm_peak": tbs * 1e3 / HBM_PEAK_GBS}
+    out["TB_per_s"] = max(out["width16"]["TB_per_s"], out["width4"]["TB_per_s"])
+    return out
+
+
+def dispatch_gaps(trace_csv, kernel="k_march_batch", round_trip_ns=200000):
+    """Idle time between consecutive dispatches of the batched step kernel in
+    a rocprofv3 kernel trace (CSV).  Dispatches closer than round_trip_ns
+    belong to one lq_batch_step call (launches queued back to back); a longer
+    gap is the host's admission and retirement between calls.  Returns the
+    busy time of the step kernels, the idle time between back-to-back
+    dispatches, and their ratio."""
+    import csv
+
+    rows = []
+    with open(trace_csv) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    rows.sort()
+    steps = [(a, b) for a, b, n in rows if kernel in n]
+    busy = sum(b - a for a, b in steps)
+    gaps_in, gaps_out, n_in = 0, 0, 0
+    prev_end = None
+    for a, b, n in rows:
+        if prev_end is not None and kernel in n:
+            g = max(a - prev_end, 0)
+            if g < round_trip_ns:
+                gaps_in += g
+                n_in += 1
+            else:
+                gaps_out += g
+        prev_end = b if prev_end is None else max(prev_end, b)
+    return {"kernel": kernel, "dispatches": len(steps), "busy_ms": busy / 1e6,
+            "idle_back_to_back_ms": gaps_in / 1e6, "back_to_back_gaps": n_in,
+            "mean_gap_us": gaps_in / max(n_in, 1) / 1e3,
+            "idle_frac_of_busy": gaps_in / max(busy, 1),
+            "idle_between_calls_ms": gaps_out / 1e6, "round_trip_threshold_us": round_trip_ns / 1e3}
 
 
 def main():
@@ -537,6 +747,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run of an FP32 workload")
+    ap.add_argument("--serving-only", action="store_true", help="only run the serving stream")
+    ap.add_argument("--dispatch-gaps", metavar="KERNEL_TRACE_CSV",
+                    help="only analyse a rocprofv3 kernel trace: idle time between batched step dispatches")
+    ap.add_argument("--precision-minima", action="store_true",
+                    help="only compare the converged minima of the FP32 form and FP64 on the 128^3 colloid slab")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--no-minimizers", action="store_true",
                     help="skip the gradient-descent / Nesterov step timings")
@@ -580,6 +796,15 @@ def main():
     if args.convergence:
         print(json.dumps({"convergence": convergence_leg()}), flush=True)
         return
+    if args.dispatch_gaps:
+        print(json.dumps({"dispatch_gaps": dispatch_gaps(args.dispatch_gaps)}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_leg(args.serving_requests)}), flush=True)
+        return
+    if args.precision_minima:
+        print(json.dumps({"precision_minima": precision_minima()}), flush=True)
+        return
     if args.step_scaling:
         print(json.dumps({"step_scaling": step_scaling_leg()}), flush=True)
         return
@@ -611,7 +836,7 @@ def main():
         "config": describe(cfg),
         "simulated_site_updates_per_s": g["n_sim"] * args.steps / g["wall_s"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["name"]),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["name"], cfg["prec"]),
                      "kernel": "k_march<fused FIRE step>", "kernel_ms": g["kernel_ms"],
                      "algorithmic_bytes_per_launch": alg_bytes},
         "energy_start_end": [g["E0"], g["E1"]],
@@ -621,15 +846,27 @@ def main():
         cc = copy_ceiling()
         out["roofline"]["copy_ceiling_GBs"] = cc["TB_per_s"] * 1e3
         out["roofline"]["frac_of_copy_ceiling"] = achieved / (cc["TB_per_s"] * 1e3)
+    if cfg["prec"] == "f32" and not args.no_fp64:
+        # the same workload at the paper's precision (FP64 state), same steps
+        print("[bench] the same workload in FP64", file=sys.stderr, flush=True)
+        c64 = dict(cfg, prec="f64")
+        g64 = gpu_leg(c64, args.steps, args.warmup)
+        ach64 = g64["bytes_per_site"] * g64["N"] / (g64["kernel_ms"] * 1e-3) / 1e9
+        out["fp64"] = {
+            "value": g64["N"] * args.steps / g64["wall_s"], "unit": "site-updates/s",
+            "ms_per_step": 1e3 * g64["wall_s"] / args.steps, "dtype": "f64",
+            "roofline": {"bound": "hbm", "achieved": ach64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach64 / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["name"], "f64"),
+                         "kernel": "k_march<fused FIRE step>", "kernel_ms": g64["kernel_ms"],
+                         "algorithmic_bytes_per_launch": g64["bytes_per_site"] * g64["N"]},
+            "energy_start_end": [g64["E0"], g64["E1"]]}
     if not args.no_precision and cfg["prec"] == "f32":
         print("[bench] precision form", file=sys.stderr, flush=True)
-        out["precision"] = precision_leg(cfg)
+        out["precision"] = {cfg["name"]: precision_leg(cfg)}
         if cfg["name"] == "multi_colloid256":
-            # the 128^3 colloid slab (walls, colloid, L2/L3) in both precisions
-            from paper_1911_07045_amd import synth
-
-            slab = synth.colloid_slab(128)
-            out["precision"]["colloid_slab128"] = precision_leg(slab)
+            # the 128^3 colloid slab against the oracle's stored FP64 schedule
+            print("[bench] precision form against the stored oracle schedule", file=sys.stderr, flush=True)
+            out["precision"]["colloid_slab128"] = precision_vs_oracle()
     if not args.no_minimizers:
         print("[bench] gradient descent / Nesterov steps", file=sys.stderr, flush=True)
         out["minimizers"] = minimizer_leg(cfg)

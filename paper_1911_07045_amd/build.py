@@ -20,6 +20,7 @@ DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-pa
 SOURCES = [
     ("kernels.hip", DEVICE),
     ("noalloc.hip", DEVICE),
+    ("stream_copy.hip", DEVICE),
     ("abi.cpp", []),
     ("geometry.cpp", ["-ffp-contract=off"]),
 ]

@@ -731,6 +731,25 @@ int lq_minimize_noalloc(lq_lattice* lat, const lq_fire_params* fp, void* q, void
     return rc;
 }
 
+int lq_stream_copy(const void* const* src, void* const* dst, int32_t n_streams, int64_t bytes, int32_t width,
+                   void* stream) {
+    if (!src || !dst || n_streams < 1 || n_streams > STREAMS_MAX)
+        return fail(nullptr, LQ_EINVAL, "n_streams must lie in 1..16 with src and dst arrays");
+    if (width != 4 && width != 16) return fail(nullptr, LQ_EINVAL, "width must be 4 or 16 bytes");
+    if (bytes <= 0 || bytes > ((int64_t)1 << 31) || bytes % width != 0)
+        return fail(nullptr, LQ_EINVAL, "bytes must be a positive multiple of width, at most 2^31");
+    StreamSet p{};
+    for (int i = 0; i < n_streams; ++i) {
+        if (!src[i] || !dst[i] || ((uintptr_t)src[i] % 16) != 0 || ((uintptr_t)dst[i] % 16) != 0)
+            return fail(nullptr, LQ_EINVAL, "stream buffers must be non-NULL and 16-byte aligned");
+        p.src[i] = src[i];
+        p.dst[i] = dst[i];
+    }
+    const int rc = launch_stream_copy(p, n_streams, bytes, width, stream);
+    if (rc != LQ_OK) return fail(nullptr, rc, "kernel launch failed");
+    return LQ_OK;
+}
+
 const char* lq_last_error(const lq_lattice* lat) { return lat ? lat->err.c_str() : g_err.c_str(); }
 
 }  // extern "C"

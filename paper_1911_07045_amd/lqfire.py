@@ -134,6 +134,7 @@ def lib():
             "lq_descent_minimize": (C.c_int, [vp, C.POINTER(DescentParams), vp, vp, vp, vp, i64,
                                               C.POINTER(MinResult)]),
             "lq_director_field": (C.c_int, [vp, vp, vp, vp, vp, C.c_double, C.POINTER(C.c_int64)]),
+            "lq_stream_copy": (C.c_int, [C.POINTER(vp), C.POINTER(vp), i32, i64, i32, vp]),
             "lq_last_error": (C.c_char_p, [vp]),
             "lq_batch_create": (C.c_int, [i32, vp, C.POINTER(vp)]),
             "lq_batch_destroy": (C.c_int, [vp]),
@@ -472,6 +473,23 @@ class Batch:
         if rc not in (LQ_OK, LQ_ENONFINITE):
             _check(rc)
         return [reps[i] for i in range(n)]
+
+
+def stream_copy(src, dst, width=16, stream=None):
+    """lq_stream_copy: copies each device tensor of src into the matching one
+    of dst (same byte size) with the step kernel's streaming pattern; only
+    enqueues on stream (default: torch's current stream)."""
+    import torch
+    if len(src) != len(dst) or not src:
+        raise ValueError("src and dst must be equally long and non-empty")
+    nbytes = src[0].numel() * src[0].element_size()
+    for a, b in zip(src, dst):
+        if a.numel() * a.element_size() != nbytes or b.numel() * b.element_size() != nbytes:
+            raise ValueError("every stream must have the same byte size")
+    s = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+    sp = (C.c_void_p * len(src))(*[t.data_ptr() for t in src])
+    dp = (C.c_void_p * len(dst))(*[t.data_ptr() for t in dst])
+    _check(lib().lq_stream_copy(sp, dp, len(src), nbytes, int(width), C.c_void_p(s)))
 
 
 def lattice_from_config(cfg, prec=None, **kw) -> Lattice:

@@ -108,7 +108,7 @@ def test_server_results_equal_alone_and_budget_holds():
         lat.close()
     sizes = sorted(serve.request_bytes(r) for r in reqs)
     budget = sizes[-1] + sizes[-2] + 1   # at most two large requests at once
-    srv = serve.Server(max_members=3, hbm_budget=budget, chunk=40, keep_states=True)
+    srv = serve.Server(max_members=3, hbm_budget=budget, chunk=40, keep_states=True, polish_steps=0)
     peak = []
     orig_admit = srv.admit
 
@@ -186,3 +186,58 @@ def test_destroying_a_member_leaves_its_batch():
     assert rep.step == 26
     for h in held[1:]:
         h[0].close()
+
+
+def test_server_polishes_fp32_minima_in_fp64():
+    """An FP32 request whose tolerance lies below the FP32 floor runs in FP32
+    to the floor, then continues from that state in FP64 (a fresh FIRE start,
+    at most polish_steps steps) in the server's second batch: the served
+    result equals that two-stage run done alone, bit for bit.  (The floor is
+    raised here so that the FP32 phase ends within a few dozen steps.)"""
+    say("[serve] FP64 polish from the FP32 minimum")
+    floor = 2.0
+    reqs = _reqs(3, 26, force_tol=1e-7, max_steps=5000)
+    solo = {}
+    for r in reqs:
+        lat = lqfire.lattice_from_config(r, prec="f32")
+        dirs = torch.from_numpy(np.ascontiguousarray(synth.random_directors(r["dir_seed"], lat.N))).cuda()
+        q = lat.set_uniaxial(dirs, lat.empty())
+        v, F = lat.empty(), lat.empty()
+        lat.fire_init(lqfire.fire_params_from_config(r, force_tol=floor), q, v, F)
+        rep = lat.fire_step(5000)
+        assert rep.status == lqfire.CONVERGED
+        lat64 = lqfire.lattice_from_config(r, prec="f64")
+        q64 = q.double().contiguous()
+        v64, F64 = lat64.empty(), lat64.empty()
+        lat64.fire_init(lqfire.fire_params_from_config(r, max_steps=150), q64, v64, F64)
+        rep64 = lat64.fire_step(150)
+        solo[r["id"]] = (rep.step, q64.cpu(), rep64.step, rep64.status)
+        lat.close()
+        lat64.close()
+    srv = serve.Server(max_members=2, chunk=40, keep_states=True, polish_steps=150, fp32_floor=floor)
+    results = srv.run(reqs, realtime=False)
+    assert len(results) == 3
+    for res in results:
+        steps32, q64, steps, status = solo[res.id]
+        assert res.polished and res.steps == steps32
+        assert res.polish_steps == steps and res.status == status
+        assert torch.equal(srv.states[res.id][0], q64)
+    s = serve.summarize(results, srv.wall_s, srv.busy_s)
+    assert s["polished"]["count"] == 3
+
+
+def test_server_refuses_a_request_beyond_its_budget():
+    """A request that needs more device memory than the whole budget is
+    refused at arrival (the loop does not wait for it), and the others are
+    served."""
+    say("[serve] refusal beyond the budget")
+    reqs = _reqs(3, 27, force_tol=1e-3, max_steps=100)
+    reqs[1]["shape"] = (64, 64, 64)
+    budget = max(serve.request_bytes(r, "f64") for i, r in enumerate(reqs) if i != 1)
+    srv = serve.Server(max_members=2, hbm_budget=budget, chunk=50)
+    results = srv.run(reqs, realtime=False)
+    by_id = {r.id: r for r in results}
+    assert by_id[1].status == serve.REFUSED
+    assert by_id[0].status != serve.REFUSED and by_id[2].status != serve.REFUSED
+    s = serve.summarize(results, srv.wall_s, srv.busy_s)
+    assert s["refused"] == 1 and s["requests"] == 3
