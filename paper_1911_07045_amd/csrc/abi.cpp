@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -33,7 +34,8 @@ struct lq_lattice {
     // device geometry
     uint8_t* d_mask = nullptr;
     uint8_t* d_tile = nullptr;
-    uint64_t* d_tile_planes = nullptr;
+    PlaneBits* d_tile_planes = nullptr;
+    Chunk* d_chunks = nullptr;
     int32_t* d_anch_index = nullptr;
     double* d_anch_data = nullptr;
     void* d_anch_force = nullptr;  // K upper triangle and b of each row, in the field's element type
@@ -141,76 +143,167 @@ static int check_dev_ptr(lq_lattice* lat, const void* ptr, const char* name) {
     return LQ_OK;
 }
 
-// z-chunk per block: as long as possible while the grid keeps >= 2048 blocks
-// Planes per block: the longest march (at most 64 planes, so the two halo
-// planes cost at most 1/32 of the traffic) that still gives every compute
-// unit its full complement of resident blocks, and at least 4.
-static int pick_zc(const lq_params& p, int device, bool l23, int wide) {
-    const char* env = std::getenv("LQ_ZC");
-    if (env) {
-        int z = std::atoi(env);
-        if (z >= 1 && z <= 4096) return z;
-    }
+// Resident blocks of the fused step kernel on the whole device.
+static int64_t resident_blocks(const lq_params& p, int device, bool l23, int wide) {
     int n_cu = 0;
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n_cu <= 0)
         n_cu = 256;
-    const int64_t resident = (int64_t)n_cu * step_blocks_per_cu(p.prec, l23, wide);
-    const int tx = tile_x(p.prec, l23, wide), ty = tile_y(p.prec, l23, wide);
-    const int64_t ntx = (p.n[0] + tx - 1) / tx, nty = (p.n[1] + ty - 1) / ty;
-    int zc = 64;
-    while (zc > 4 && ntx * nty * ((p.n[2] + zc - 1) / zc) < resident) zc /= 2;
-    return zc;
+    return (int64_t)n_cu * step_blocks_per_cu(p.prec, l23, wide);
 }
 
-// Per tile: whether every site of the padded tile over the whole march is
-// a full bulk site (mask M_FULL), and per plane of the march whether that
-// holds for the plane and both its z-neighbours.
-static void tile_flags(const lq_params& p, bool l23, int wide, const std::vector<uint8_t>& mask, int zc,
-                       int ntx, int nty, int ntz, std::vector<uint8_t>& out, std::vector<uint64_t>& planes) {
+// Work of the step kernels.  A block marches one chunk: a run of planes of
+// one X x Y column tile.  A plane whose 3 x 3 x 3 neighbourhoods over the
+// padded tile are all full bulk sites takes the bulk evaluation; the other
+// planes (walls, colloid surfaces) cost about three times as much with L2/L3
+// (measured).  When the columns fit in one wave of resident blocks with
+// chunks of up to CHUNK_MAX planes, the grid holds one wave: with L2/L3,
+// chunks are handed out one at a time to the column whose chunks cost most,
+// and every column is cut at equal-cost points (at least 4 planes per
+// chunk), so that a step lasts about as long as the average block rather
+// than as long as the block that holds a colloid; one-constant lattices,
+// whose boundary planes cost little more, get the same equal-length cuts in
+// every column, so that neighbouring tiles march the same planes at the same
+// time and share their halo planes in L2 (measured faster than cost-balanced
+// cuts on the 256^3 multi-colloid box).  Larger lattices take 64-plane
+// chunks, which their many waves balance by themselves.  Chunks are listed
+// by their rank within the column, then by tile row and column, so that
+// neighbouring tiles are neighbours in the list.  Per chunk: whether every
+// site of the padded tile over the whole march is a full bulk site, and per
+// plane whether that holds for the plane and both its z-neighbours.  LQ_ZC
+// (1 .. CHUNK_MAX) forces chunks of that many planes.
+struct ChunkPlan {
+    std::vector<Chunk> chunks;
+    std::vector<uint8_t> bulk;
+    std::vector<PlaneBits> planes;
+};
+
+static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vector<uint8_t>& mask,
+                        int64_t resident, ChunkPlan& out) {
     const int64_t TX = tile_x(p.prec, l23, wide), TY = tile_y(p.prec, l23, wide);
     const int64_t nx = p.n[0], ny = p.n[1], nz = p.n[2];
-    out.assign((size_t)ntx * nty * ntz, 0);
-    planes.assign((size_t)ntx * nty * ntz, 0);
+    const int64_t ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, ncol = ntx * nty;
     auto wrap = [](int64_t g, int64_t n, bool per) -> int64_t {
         if (g >= 0 && g < n) return g;
         if (!per) return -1;
         g %= n;
         return g < 0 ? g + n : g;
     };
-    std::vector<uint8_t> full;  // per plane z0 - 1 .. z0 + zc of one tile
-    for (int bz = 0; bz < ntz; ++bz)
-        for (int by = 0; by < nty; ++by)
-            for (int bx = 0; bx < ntx; ++bx) {
-                const int64_t z0 = (int64_t)bz * zc, zc_eff = std::min<int64_t>(zc, nz - z0);
-                full.assign((size_t)zc_eff + 2, 0);
-                for (int64_t i = 0; i < zc_eff + 2; ++i) {
-                    const int64_t wz = wrap(z0 - 1 + i, nz, p.periodic[2]);
-                    bool ok = wz >= 0;
-                    for (int64_t y = (int64_t)by * TY - 1; ok && y <= (int64_t)by * TY + TY; ++y) {
-                        const int64_t wy = wrap(y, ny, p.periodic[1]);
-                        if (wy < 0) { ok = false; break; }
-                        for (int64_t x = (int64_t)bx * TX - 1; x <= (int64_t)bx * TX + TX; ++x) {
-                            const int64_t wx = wrap(x, nx, p.periodic[0]);
-                            if (wx < 0 || mask[wx + nx * (wy + ny * wz)] != M_FULL) { ok = false; break; }
-                        }
-                    }
-                    full[i] = ok ? 1 : 0;
+    // full[c][i]: padded plane z = i - 1 (i = 0 .. nz + 1) of column c is all M_FULL
+    const int64_t P = nz + 2;
+    std::vector<uint8_t> full((size_t)(ncol * P), 0);
+    for (int64_t c = 0; c < ncol; ++c) {
+        const int64_t bx = c % ntx, by = c / ntx;
+        for (int64_t i = 0; i < P; ++i) {
+            const int64_t wz = wrap(i - 1, nz, p.periodic[2]);
+            bool ok = wz >= 0;
+            for (int64_t y = by * TY - 1; ok && y <= by * TY + TY; ++y) {
+                const int64_t wy = wrap(y, ny, p.periodic[1]);
+                if (wy < 0) { ok = false; break; }
+                for (int64_t x = bx * TX - 1; x <= bx * TX + TX; ++x) {
+                    const int64_t wx = wrap(x, nx, p.periodic[0]);
+                    if (wx < 0 || mask[wx + nx * (wy + ny * wz)] != M_FULL) { ok = false; break; }
                 }
-                bool all = true;
-                uint64_t bits = 0;
-                for (int64_t i = 0; i < zc_eff + 2; ++i) all = all && full[i];
-                for (int64_t f = 0; f < std::min<int64_t>(zc_eff, 64); ++f)
-                    if (full[f] && full[f + 1] && full[f + 2]) bits |= (uint64_t)1 << f;
-                const size_t t = bx + (size_t)ntx * (by + (size_t)nty * bz);
-                out[t] = all ? 1 : 0;
-                planes[t] = bits;
             }
+            full[(size_t)(c * P + i)] = ok ? 1 : 0;
+        }
+    }
+    auto F = [&](int64_t c, int64_t i) { return full[(size_t)(c * P + i)] != 0; };
+    // cum[c][f]: cost of planes 0 .. f - 1 of column c
+    const double g = 3.0;
+    std::vector<double> cum((size_t)(ncol * (nz + 1)), 0.0);
+    for (int64_t c = 0; c < ncol; ++c)
+        for (int64_t f = 0; f < nz; ++f) {
+            const bool bulk = F(c, f) && F(c, f + 1) && F(c, f + 2);
+            cum[(size_t)(c * (nz + 1) + f + 1)] = cum[(size_t)(c * (nz + 1) + f)] + (bulk ? 1.0 : g);
+        }
+    auto total = [&](int64_t c) { return cum[(size_t)(c * (nz + 1) + nz)]; };
+    // one wave: chunks up to CHUNK_MAX planes, cost-balanced; many waves: 64 planes
+    const int64_t zmin = 4;
+    const bool one_wave = ncol * ((nz + CHUNK_MAX - 1) / CHUNK_MAX) <= resident;
+    const int64_t zmax = one_wave ? CHUNK_MAX : 64;
+    const int64_t m_lo = (nz + zmax - 1) / zmax;
+    const int64_t m_hi = std::max<int64_t>(m_lo, nz / zmin);
+    std::vector<int64_t> m((size_t)ncol, m_lo);
+    const char* env = std::getenv("LQ_ZC");
+    const int zfix = env ? std::atoi(env) : 0;
+    std::vector<std::pair<int64_t, Chunk>> list;  // (rank within the column, chunk)
+    if (zfix >= 1 && zfix <= CHUNK_MAX) {
+        for (int64_t c = 0; c < ncol; ++c)
+            for (int64_t z0 = 0, k = 0; z0 < nz; z0 += zfix, ++k)
+                list.push_back({k, Chunk{(int32_t)((c % ntx) * TX), (int32_t)((c / ntx) * TY), (int32_t)z0,
+                                         (int32_t)std::min<int64_t>(zfix, nz - z0)}});
+    } else {
+        if (one_wave && !l23) {
+            // one-constant lattices: the same cuts in every column (a general
+            // plane costs little more than a bulk one here, and aligned chunks
+            // let neighbouring tiles share their halo planes in L2)
+            const int64_t mu = std::min(std::max(m_lo, resident / std::max<int64_t>(ncol, 1)), m_hi);
+            for (int64_t c = 0; c < ncol; ++c) m[(size_t)c] = mu;
+        }
+        // L2/L3: one more chunk at a time to the column whose chunks cost
+        // most, until the chunks fill one wave of resident blocks (this
+        // minimizes the largest chunk cost for that many chunks)
+        std::priority_queue<std::pair<double, int64_t>> heavy;
+        for (int64_t c = 0; c < ncol; ++c) heavy.push({total(c) / (double)m_lo, c});
+        for (int64_t blocks = ncol * m_lo; one_wave && l23 && blocks < resident && !heavy.empty();) {
+            const int64_t c = heavy.top().second;
+            heavy.pop();
+            if (m[(size_t)c] >= m_hi) continue;
+            ++m[(size_t)c];
+            ++blocks;
+            heavy.push({total(c) / (double)m[(size_t)c], c});
+        }
+        for (int64_t c = 0; c < ncol; ++c) {
+            const int64_t mc = m[(size_t)c];
+            const double* cc = &cum[(size_t)(c * (nz + 1))];
+            int64_t z0 = 0;
+            for (int64_t k = 1; k <= mc; ++k) {
+                int64_t z1 = nz;
+                if (k < mc && !l23) {
+                    z1 = nz * k / mc;  // equal plane counts
+                } else if (k < mc) {
+                    // cut where the cost reaches k/mc of the column's, leaving every
+                    // later chunk at least one plane and at most zmax
+                    const double target = total(c) * (double)k / (double)mc;
+                    const int64_t lo_z = std::max(z0 + 1, nz - zmax * (mc - k));
+                    const int64_t hi_z = std::min(z0 + zmax, nz - (mc - k));
+                    z1 = lo_z;
+                    while (z1 < hi_z && cc[z1] < target) ++z1;
+                    if (z1 > lo_z && cc[z1] - target > target - cc[z1 - 1]) --z1;
+                }
+                list.push_back({k - 1, Chunk{(int32_t)((c % ntx) * TX), (int32_t)((c / ntx) * TY), (int32_t)z0,
+                                             (int32_t)(z1 - z0)}});
+                z0 = z1;
+            }
+        }
+    }
+    std::stable_sort(list.begin(), list.end(),
+                     [](const std::pair<int64_t, Chunk>& a, const std::pair<int64_t, Chunk>& b) {
+                         return a.first < b.first;
+                     });
+    out.chunks.clear();
+    out.bulk.clear();
+    out.planes.clear();
+    for (const auto& e : list) {
+        const Chunk& ch = e.second;
+        const int64_t c = ch.x0 / TX + ntx * (ch.y0 / TY);
+        bool all = true;
+        for (int64_t i = ch.z0; i <= ch.z0 + ch.zc + 1; ++i) all = all && F(c, i);
+        PlaneBits bits{};
+        for (int64_t f = 0; f < std::min<int64_t>(ch.zc, CHUNK_MAX); ++f)
+            if (F(c, ch.z0 + f) && F(c, ch.z0 + f + 1) && F(c, ch.z0 + f + 2))
+                bits.w[f / 64] |= (uint64_t)1 << (f % 64);
+        out.chunks.push_back(ch);
+        out.bulk.push_back(all ? 1 : 0);
+        out.planes.push_back(bits);
+    }
 }
 
 static void free_geometry(lq_lattice* lat) {
     if (lat->d_mask) (void)hipFree(lat->d_mask);
     if (lat->d_tile) (void)hipFree(lat->d_tile);
     if (lat->d_tile_planes) (void)hipFree(lat->d_tile_planes);
+    if (lat->d_chunks) (void)hipFree(lat->d_chunks);
     if (lat->d_anch_index) (void)hipFree(lat->d_anch_index);
     if (lat->d_anch_data) (void)hipFree(lat->d_anch_data);
     if (lat->d_anch_force) (void)hipFree(lat->d_anch_force);
@@ -219,6 +312,7 @@ static void free_geometry(lq_lattice* lat) {
     lat->d_anch_index = nullptr;
     lat->d_anch_data = nullptr;
     lat->d_anch_force = nullptr;
+    lat->d_chunks = nullptr;
 }
 
 // Uploads a rasterized geometry and refreshes the device view.
@@ -233,20 +327,20 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     d.N = lat->N;
     d.A = p.A; d.B = p.B; d.C = p.C; d.L1 = p.L1; d.L2 = p.L2; d.L3 = p.L3; d.L4 = p.L4;
     d.wide = tile_wide_for(p.n[0], p.prec, lat->l23);
-    d.zc = pick_zc(p, lat->device, lat->l23, d.wide);
-    const int tx = tile_x(p.prec, lat->l23, d.wide), ty = tile_y(p.prec, lat->l23, d.wide);
-    d.ntx = (int)((p.n[0] + tx - 1) / tx);
-    d.nty = (int)((p.n[1] + ty - 1) / ty);
-    d.ntz = (int)((p.n[2] + d.zc - 1) / d.zc);
-    std::vector<uint8_t> tiles;
-    std::vector<uint64_t> tile_planes;
-    tile_flags(p, lat->l23, d.wide, g.mask, d.zc, d.ntx, d.nty, d.ntz, tiles, tile_planes);
+    ChunkPlan plan;
+    plan_chunks(p, lat->l23, d.wide, g.mask, resident_blocks(p, lat->device, lat->l23, d.wide), plan);
+    d.nchunks = (int)plan.chunks.size();
+    const std::vector<uint8_t>& tiles = plan.bulk;
+    const std::vector<PlaneBits>& tile_planes = plan.planes;
+    HIPCHK(lat, hipMalloc(&lat->d_chunks, plan.chunks.size() * sizeof(Chunk)));
+    HIPCHK(lat, hipMemcpy(lat->d_chunks, plan.chunks.data(), plan.chunks.size() * sizeof(Chunk),
+                          hipMemcpyHostToDevice));
     HIPCHK(lat, hipMalloc(&lat->d_mask, (size_t)lat->N));
     HIPCHK(lat, hipMemcpy(lat->d_mask, g.mask.data(), (size_t)lat->N, hipMemcpyHostToDevice));
     HIPCHK(lat, hipMalloc(&lat->d_tile, tiles.size()));
     HIPCHK(lat, hipMemcpy(lat->d_tile, tiles.data(), tiles.size(), hipMemcpyHostToDevice));
-    HIPCHK(lat, hipMalloc(&lat->d_tile_planes, tile_planes.size() * sizeof(uint64_t)));
-    HIPCHK(lat, hipMemcpy(lat->d_tile_planes, tile_planes.data(), tile_planes.size() * sizeof(uint64_t),
+    HIPCHK(lat, hipMalloc(&lat->d_tile_planes, tile_planes.size() * sizeof(PlaneBits)));
+    HIPCHK(lat, hipMemcpy(lat->d_tile_planes, tile_planes.data(), tile_planes.size() * sizeof(PlaneBits),
                           hipMemcpyHostToDevice));
     lat->n_anch = (int)g.anch_site.size();
     if (lat->n_anch > 0) {
@@ -277,6 +371,7 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
         }
     }
     d.mask = lat->d_mask;
+    d.chunks = lat->d_chunks;
     d.tile_bulk = lat->d_tile;
     d.tile_planes = lat->d_tile_planes;
     d.n_anch = lat->n_anch;

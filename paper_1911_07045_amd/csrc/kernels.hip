@@ -688,6 +688,14 @@ __device__ __forceinline__ void ring_pos(int r, int& px, int& py) {
     else { px = PX - 1; py = r - 2 * PX - (PY - 2) + 1; }
 }
 
+// Plane f (1-based within the march) of a chunk takes the bulk evaluation.
+__device__ __forceinline__ bool bulk_plane_of(const PlaneBits& b, int f) {
+    const int i = f - 1;
+    if (i < 0 || i >= CHUNK_MAX) return false;
+    const uint64_t w = i < 64 ? b.w[0] : (i < 128 ? b.w[1] : (i < 192 ? b.w[2] : b.w[3]));
+    return (w >> (i & 63)) & 1u;
+}
+
 #ifndef LQ_PREFETCH
 #define LQ_PREFETCH 1
 #endif
@@ -700,7 +708,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                                       T* __restrict__ F_out, T cv, T cF, T dt, T hdt, int x0, int y0,
                                       int z0, int zc, T (*sq)[5][Tile<T, L23, W>::PY][Tile<T, L23, W>::PX],
                                       uint8_t (*sm)[Tile<T, L23, W>::PY][Tile<T, L23, W>::PX], double red[4],
-                                      uint64_t plane_bulk) {
+                                      const PlaneBits plane_bulk) {
     using G = Tile<T, L23, W>;
     constexpr int NS = 4;
     constexpr int PF = LQ_PREFETCH;  // planes of raw data in flight
@@ -856,7 +864,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
         AnchRow<T> A;
         if (!BULK && W == 1) {
             const int f = j - 1;
-            const bool bulk_plane = f >= 1 && f <= 64 && ((plane_bulk >> (f - 1)) & 1);
+            const bool bulk_plane = bulk_plane_of(plane_bulk, f);
             // only waves with an anchored site issue the loads
             if (!bulk_plane && __builtin_amdgcn_ballot_w64((m_newer & M_ANCH) != 0) != 0)
                 anch_load(L, (m_newer & M_ANCH) ? a_newer : 0, A);
@@ -894,7 +902,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
             // takes the bulk evaluation also inside a boundary tile (wide
             // tiles only: the narrow ones serve small boxes, where few planes
             // qualify and the extra code costs registers)
-            if (W == 1 && !BULK && f >= 1 && f <= 64 && ((plane_bulk >> (f - 1)) & 1)) {
+            if (W == 1 && !BULK && bulk_plane_of(plane_bulk, f)) {
                 Stencil<T, L23, true, W> PB;
                 PB.q = sq; PB.m = sm;
                 PB.s[0] = P.s[0]; PB.s[1] = P.s[1]; PB.s[2] = P.s[2];
@@ -963,15 +971,14 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
                                            int nblocks, int bid) {
     constexpr int NS = 4;
     using G = Tile<T, L23, W>;
-    constexpr int TX = G::X, TY = G::Y, PX = G::PX, PY = G::PY;
+    constexpr int PX = G::PX, PY = G::PY;
     __shared__ T sq[NS][5][PY][PX];
     __shared__ uint8_t sm[NS][PY][PX];
     __shared__ double scratch[G::N / 64][4];
     __shared__ int last_flag;
 
-    const int bx = bid % L.ntx, by = (bid / L.ntx) % L.nty, bz = bid / (L.ntx * L.nty);
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * L.zc;
-    const int zc = min(L.zc, L.nz - z0);
+    const Chunk ch = L.chunks[bid];
+    const int x0 = ch.x0, y0 = ch.y0, z0 = ch.z0, zc = ch.zc;
 
     constexpr bool STEP = MODE != MODE_FORCE;
     const T *q_in, *v_in = nullptr, *F_in = nullptr;
@@ -992,12 +999,16 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
         F_out = Fout;
     }
     double red[4] = {0.0, 0.0, 0.0, 0.0};
-    if (L.tile_bulk[bid])
+    if (L.tile_bulk[bid]) {
+        PlaneBits all;
+#pragma unroll
+        for (int i = 0; i < PLANE_WORDS; ++i) all.w[i] = ~(uint64_t)0;
         march<T, L23, MODE, true, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
-                                  sq, sm, red, ~(uint64_t)0);
-    else
+                                  sq, sm, red, all);
+    } else {
         march<T, L23, MODE, false, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
                                    sq, sm, red, L.tile_planes[bid]);
+    }
     if (STEP) grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
 }
 
@@ -1404,7 +1415,7 @@ __global__ __launch_bounds__(256) void k_directors(LatDev L, const T* __restrict
 // launchers
 static int hip_status(hipError_t e) { return e == hipSuccess ? LQ_OK : LQ_EHIP; }
 
-int64_t n_step_blocks(const LatDev& L) { return (int64_t)L.ntx * L.nty * L.ntz; }
+int64_t n_step_blocks(const LatDev& L) { return L.nchunks; }
 
 // Resident blocks per compute unit of the fused FIRE step kernel.
 template <typename T, bool L23, int W>

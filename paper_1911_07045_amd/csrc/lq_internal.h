@@ -117,23 +117,36 @@ inline int tile_threads(int prec, bool l23, int wide) { return tile_x(prec, l23,
 // a lattice narrower than one wide tile takes the narrow one
 inline int tile_wide_for(int64_t nx, int prec, bool l23) { return nx >= tile_x_w<1>(prec, l23) ? 1 : 0; }
 
+// One block's work in the step kernels: the X x Y column tile at (x0, y0)
+// over planes z0 .. z0 + zc - 1, zc <= CHUNK_MAX.
+struct Chunk {
+    int32_t x0, y0, z0, zc;
+};
+// Per-chunk plane flags: bit i % 64 of word i / 64 is set when plane z0 + i
+// and both its z-neighbours are M_FULL over the padded tile.
+constexpr int PLANE_WORDS = 4;
+constexpr int CHUNK_MAX = 64 * PLANE_WORDS;
+struct PlaneBits {
+    uint64_t w[PLANE_WORDS];
+};
+
 // Device view of a lattice.
 struct LatDev {
     int nx, ny, nz;
     int per[3];
     int64_t N;
     const uint8_t* mask;
-    const uint8_t* tile_bulk;  // 1: every site of the padded tile has mask M_FULL
-    const uint64_t* tile_planes;  // bit i: plane z0 + i of the tile and both its z-neighbours are
-                                  // M_FULL over the padded tile (the first 64 planes of a march)
+    const Chunk* chunks;       // per block of the step kernels
+    const uint8_t* tile_bulk;  // per chunk, 1: every site of the padded tile has mask M_FULL
+    const PlaneBits* tile_planes;  // per chunk
     int n_anch;
     const int32_t* anch_index;  // per site: 1 + row of anch_data, 0 when not anchored
     const double* anch_data;    // ANCH_STRIDE per anchored site
     const void* anch_force;     // ANCH_FSTRIDE per anchored site, element type of the field
     double ext[5];              // constant external-field force per simulated site
     double A, B, C, L1, L2, L3, L4;
-    int zc, ntx, nty, ntz;
-    int wide;  // tile width kind of the step kernels (1 wide, 0 narrow)
+    int nchunks;  // blocks of one step launch
+    int wide;     // tile width kind of the step kernels (1 wide, 0 narrow)
 };
 
 // FIRE state kept in device memory.

@@ -12,7 +12,14 @@ namespace {
 
 // Non-temporal store policy: bit 1 of the buffer instruction's cache-policy
 // operand on gfx950, the policy of the step kernel's stores of q, v, F.
-constexpr int STORE_POLICY = 2;
+#ifndef LQ_COPY_POLICY
+#define LQ_COPY_POLICY 2
+#endif
+constexpr int STORE_POLICY = LQ_COPY_POLICY;
+// Blocks of one launch at most (grid-stride beyond).
+#ifndef LQ_COPY_GRID
+#define LQ_COPY_GRID 8192
+#endif
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const void* p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
@@ -58,7 +65,7 @@ int launch_stream_copy(const StreamSet& p, int ns, int64_t bytes, int width, voi
     // enough blocks to fill every compute unit many times over; grid-stride beyond
     const int64_t per_block = 256 * (int64_t)width;
     const int64_t need = (bytes + per_block - 1) / per_block;
-    const int g = (int)(need < 8192 ? (need > 0 ? need : 1) : 8192);
+    const int g = (int)(need < LQ_COPY_GRID ? (need > 0 ? need : 1) : LQ_COPY_GRID);
     if (width == 16) k_stream_copy<16><<<g, 256, 0, s>>>(p, ns, (uint32_t)bytes);
     else k_stream_copy<4><<<g, 256, 0, s>>>(p, ns, (uint32_t)bytes);
     return hipGetLastError() == hipSuccess ? LQ_OK : LQ_EHIP;
