@@ -349,13 +349,14 @@ int lq_batch_step(lq_batch* b, int64_t n_steps, lq_fire_report* reports);
  * A FIRE step (Algorithm 1) reads q, v, F and writes them back: 15 streams in
  * and 15 out per site.  This copies n_streams device buffers of `bytes` each
  * (src[i] -> dst[i], 1..16 streams) with `width` bytes per lane per access
- * (4: one FP32 value per lane, as the step kernel loads its fields; 16: whole
- * 16-byte pieces) and the step kernel's non-temporal store policy, so that
+ * (4: one FP32 value per lane, as the FP32 step kernel loads its fields; 8:
+ * one FP64 value; 16: whole 16-byte pieces) and the step kernel's
+ * non-temporal store policy, so that
  * its time measures what plain streaming of the step's traffic reaches on
  * the device.  Buffers are the caller's device memory, 16-byte aligned, and
  * must not overlap; enqueued on `stream` (a hipStream_t, NULL for the
  * default stream), no synchronization.  LQ_EINVAL on NULL or unaligned
- * pointers, n_streams outside 1..16, width not 4 or 16, or bytes not a
+ * pointers, n_streams outside 1..16, width not 4, 8 or 16, or bytes not a
  * positive multiple of width up to 2^31. */
 int lq_stream_copy(const void* const* src, void* const* dst, int32_t n_streams, int64_t bytes, int32_t width,
                    void* stream);

@@ -165,9 +165,8 @@ static int64_t resident_blocks(const lq_params& p, int device, bool l23, int wid
 // every column, so that neighbouring tiles march the same planes at the same
 // time and share their halo planes in L2 (measured faster than cost-balanced
 // cuts on the 256^3 multi-colloid box).  Larger lattices take 64-plane
-// chunks, which their many waves balance by themselves.  Chunks are listed
-// by their rank within the column, then by tile row and column, so that
-// neighbouring tiles are neighbours in the list.  Per chunk: whether every
+// chunks, which their many waves balance by themselves (chunk order: at the
+// end of plan_chunks).  Per chunk: whether every
 // site of the padded tile over the whole march is a full bulk site, and per
 // plane whether that holds for the plane and both its z-neighbours.  LQ_ZC
 // (1 .. CHUNK_MAX) forces chunks of that many planes.
@@ -277,8 +276,20 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
             }
         }
     }
+    // One wave: by rank within the column, then tile row and column (every
+    // block runs at once; neighbouring tiles march the same planes together).
+    // Many waves: the step kernel hands each XCD a contiguous eighth of the
+    // list, so the columns are split into eight groups of neighbouring
+    // columns and each group is listed by rank, then column: every XCD then
+    // gets its share of the heavier wall chunks (by rank alone, the first and
+    // last eighths held all of them), and neighbouring columns still march
+    // the same planes together.
+    const int64_t gsize = one_wave ? ncol : (ncol + 7) / 8;
     std::stable_sort(list.begin(), list.end(),
-                     [](const std::pair<int64_t, Chunk>& a, const std::pair<int64_t, Chunk>& b) {
+                     [&](const std::pair<int64_t, Chunk>& a, const std::pair<int64_t, Chunk>& b) {
+                         const int64_t ca = a.second.x0 / TX + ntx * (a.second.y0 / TY);
+                         const int64_t cb = b.second.x0 / TX + ntx * (b.second.y0 / TY);
+                         if (ca / gsize != cb / gsize) return ca / gsize < cb / gsize;
                          return a.first < b.first;
                      });
     out.chunks.clear();
@@ -830,7 +841,7 @@ int lq_stream_copy(const void* const* src, void* const* dst, int32_t n_streams, 
                    void* stream) {
     if (!src || !dst || n_streams < 1 || n_streams > STREAMS_MAX)
         return fail(nullptr, LQ_EINVAL, "n_streams must lie in 1..16 with src and dst arrays");
-    if (width != 4 && width != 16) return fail(nullptr, LQ_EINVAL, "width must be 4 or 16 bytes");
+    if (width != 4 && width != 8 && width != 16) return fail(nullptr, LQ_EINVAL, "width must be 4, 8 or 16 bytes");
     if (bytes <= 0 || bytes > ((int64_t)1 << 31) || bytes % width != 0)
         return fail(nullptr, LQ_EINVAL, "bytes must be a positive multiple of width, at most 2^31");
     StreamSet p{};

@@ -26,8 +26,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const void* p, uin
 }
 
 // Stream i of `ns` goes from src[i] to dst[i], W bytes per lane per access
-// (4: one FP32 value per lane, as the step kernel loads its fields; 16: whole
-// 16-byte pieces); the loads of every stream are issued before the stores.
+// (4: one FP32 value per lane, as the FP32 step kernel loads its fields; 8:
+// one FP64 value; 16: whole 16-byte pieces); the loads of every stream are
+// issued before the stores.
 // `bytes` is at most 2^31, so the grid-stride offset never wraps.
 template <int W>
 __global__ __launch_bounds__(256) void k_stream_copy(StreamSet p, int ns, uint32_t bytes) {
@@ -44,6 +45,17 @@ __global__ __launch_bounds__(256) void k_stream_copy(StreamSet p, int ns, uint32
                 if (i < ns)
                     __builtin_amdgcn_raw_buffer_store_b128(v[i], stream_rsrc(p.dst[i], bytes), (int)off, 0,
                                                            STORE_POLICY);
+        } else if constexpr (W == 8) {
+            typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+            u32x2 v[STREAMS_MAX];
+#pragma unroll
+            for (int i = 0; i < STREAMS_MAX; ++i)
+                if (i < ns) v[i] = __builtin_amdgcn_raw_buffer_load_b64(stream_rsrc(p.src[i], bytes), (int)off, 0, 0);
+#pragma unroll
+            for (int i = 0; i < STREAMS_MAX; ++i)
+                if (i < ns)
+                    __builtin_amdgcn_raw_buffer_store_b64(v[i], stream_rsrc(p.dst[i], bytes), (int)off, 0,
+                                                          STORE_POLICY);
         } else {
             uint32_t v[STREAMS_MAX];
 #pragma unroll
@@ -67,6 +79,7 @@ int launch_stream_copy(const StreamSet& p, int ns, int64_t bytes, int width, voi
     const int64_t need = (bytes + per_block - 1) / per_block;
     const int g = (int)(need < LQ_COPY_GRID ? (need > 0 ? need : 1) : LQ_COPY_GRID);
     if (width == 16) k_stream_copy<16><<<g, 256, 0, s>>>(p, ns, (uint32_t)bytes);
+    else if (width == 8) k_stream_copy<8><<<g, 256, 0, s>>>(p, ns, (uint32_t)bytes);
     else k_stream_copy<4><<<g, 256, 0, s>>>(p, ns, (uint32_t)bytes);
     return hipGetLastError() == hipSuccess ? LQ_OK : LQ_EHIP;
 }

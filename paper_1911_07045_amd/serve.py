@@ -11,15 +11,18 @@ independent of its batch mates (per-request controller and block-ordered
 FP64 reductions).
 
 The FP32 form (FP32 state, FP64 reductions and controller) ends with an FP64
-polish from its FP32 minimum.  FP32 rounding puts a floor under max|F|: one
-force evaluation sums about 30 terms whose magnitudes add up to ~|H| max|q|
-(|H| ~ 36 L1 + anchoring, the stencil's infinity norm), so it is off by up
-to ~30 u |H| max|q| ~ 1e-4 (u = 2^-24).  So the FP32 run stops at
-max(tolerance, fp32_floor); a request whose tolerance lies below the floor
-then continues from that FP32 state in FP64, from a fresh FIRE start, for at
-most `polish_steps` steps in a second batch.  A request whose FP32 run
-reaches its step limit is reported as capped, without a polish.  A request
-that needs more device memory than the whole budget is refused at arrival.
+polish when FP32 rounding stops it short of the request's tolerance.  One
+FP32 force evaluation is off by up to ~30 u |H| max|q| ~ 1e-4 (30 summed
+terms, |H| ~ 36 L1 + anchoring the stencil's infinity norm, u = 2^-24), so a
+plateau of max|F| below fp32_floor = 1e-4 (no tenth's improvement of its best
+for stall_steps steps, or the step limit reached) may be rounding, or just
+slow relaxation.  The server then measures which: it evaluates the FP64 force
+of the FP32 state and compares it with the FP32 force.  When the FP32 force
+is off by at least noise_frac of its own max|F| (rounding dominates), the
+request continues from its FP32 state in FP64 (a fresh FIRE start, at most
+polish_steps steps) in a second batch; otherwise it keeps relaxing in FP32
+(or, at its step limit, is reported as capped).  A request that needs more
+device memory than the whole budget is refused at arrival.
 
 Reported per request: arrival-to-result latency, steps (FP32 and polish),
 status, final max|F| and energy, and whether it was polished.
@@ -64,6 +67,8 @@ class _Live:
     F: object
     nbytes: int
     admitted: float
+    best: float = float("inf")  # best max|F| of the FP32 phase below the floor
+    best_step: int = 0          # step at which best last fell by a tenth
     fp32_steps: int = 0         # steps of the FP32 phase (set when the polish starts)
 
 
@@ -87,7 +92,7 @@ def _lattice(req, prec):
 
 class Server:
     def __init__(self, max_members=64, hbm_budget=None, chunk=50, prec="f32", keep_states=False,
-                 polish_steps=2000, fp32_floor=1e-4):
+                 polish_steps=2000, fp32_floor=1e-4, stall_steps=1000, noise_frac=0.3):
         import torch
         self.torch = torch
         self.prec = prec
@@ -100,9 +105,12 @@ class Server:
         self.used = 0
         self.batch = lqfire.Batch(self.max_members)
         self.live: list[_Live] = []
-        # FP64 polish from the FP32 minimum of requests with a tolerance below the FP32 floor
+        # FP64 polish of FP32 requests that stall below the FP32 floor
         self.polish_steps = int(polish_steps) if prec == "f32" else 0
         self.fp32_floor = float(fp32_floor)
+        self.stall_steps = stall_steps
+        self.noise_frac = float(noise_frac)
+        self.noise_checks = 0
         self.batch64 = lqfire.Batch(self.max_members) if self.polish_steps > 0 else None
         self.polishing: list[_Live] = []
         self.keep_states = keep_states
@@ -127,7 +135,7 @@ class Server:
             synth.random_directors(req["dir_seed"], lat.N))).cuda()
         q = lat.set_uniaxial(dirs, lat.empty())
         v, F = lat.empty(), lat.empty()
-        lat.fire_init(lqfire.fire_params_from_config(req, force_tol=self._phase_tol(req)), q, v, F)
+        lat.fire_init(lqfire.fire_params_from_config(req), q, v, F)
         del dirs
         nb = self.reserve(req)
         self.used += nb
@@ -139,23 +147,35 @@ class Server:
         self.live.append(live)
         return live, None
 
-    def _phase_tol(self, req):
-        """Force tolerance of the first phase: the request's, or the FP32 floor
-        when the request asks for less and the server polishes."""
-        tol = req["fire"].get("force_tol", 1e-9)
-        return max(tol, self.fp32_floor) if self.polish_steps > 0 else tol
+    def _plateau(self, live, rep):
+        """The FP32 phase is below the FP32 floor and has stopped improving:
+        at the step limit, or without a tenth's improvement of its best
+        max|F| for stall_steps steps."""
+        if self.polish_steps <= 0 or rep.status == lqfire.CONVERGED or not rep.maxF < self.fp32_floor:
+            return False
+        if rep.status == lqfire.MAX_STEPS:
+            return True
+        if rep.maxF < 0.9 * live.best:
+            live.best, live.best_step = rep.maxF, rep.step
+        return self.stall_steps is not None and rep.step - live.best_step >= self.stall_steps
 
-    def _wants_polish(self, live, rep):
-        return (self.polish_steps > 0 and rep.status == lqfire.CONVERGED
-                and self._phase_tol(live.req) > live.req["fire"].get("force_tol", 1e-9))
-
-    def _start_polish(self, live, rep):
-        """Moves an FP32 request at its FP32 minimum to FP64: its state in an
-        FP64 lattice, a fresh FIRE start with the request's tolerance, at
-        most polish_steps steps."""
-        req = live.req
-        lat64 = _lattice(req, "f64")
+    def _rounding_bound(self, live):
+        """The FP64 lattice of the request and whether FP32 rounding
+        dominates its current force: max|F64(q) - F32(q)| >= noise_frac
+        max|F32(q)| at the FP32 state q."""
+        self.noise_checks += 1
+        lat64 = _lattice(live.req, "f64")
         q64 = live.q.double().contiguous()
+        F64 = lat64.compute_forces(q64)
+        F32 = live.F.double()
+        noise = (F64 - F32).abs().max().item()
+        return lat64, q64, noise >= self.noise_frac * F32.abs().max().item()
+
+    def _start_polish(self, live, rep, lat64, q64):
+        """Moves a stalled FP32 request to FP64: its state in the FP64
+        lattice, a fresh FIRE start with the request's tolerance, at most
+        polish_steps steps."""
+        req = live.req
         v64, F64 = lat64.empty(), lat64.empty()
         lat64.fire_init(lqfire.fire_params_from_config(req, max_steps=self.polish_steps), q64, v64, F64)
         live.lat.close()
@@ -202,13 +222,8 @@ class Server:
                 if not self.fits(req):
                     break
                 live, rep = self.admit(req, time.perf_counter() - t0)
-                if rep is not None:  # the start already meets the first phase's tolerance
-                    if self._wants_polish(live, rep):
-                        p, r0 = self._start_polish(live, rep)
-                        if r0 is not None:
-                            self._retire(p, r0, time.perf_counter() - t0, results, polished=True)
-                    else:
-                        self._retire(live, rep, time.perf_counter() - t0, results)
+                if rep is not None:  # already converged at the start
+                    self._retire(live, rep, time.perf_counter() - t0, results)
                 i += 1
             if not self.live and not self.polishing:
                 if i < len(pending):
@@ -224,12 +239,20 @@ class Server:
             now = time.perf_counter() - t0
             keep = []
             for live, rep in zip(list(self.live), reps):
-                if rep.status == lqfire.RUNNING:
+                polish = None
+                if self._plateau(live, rep):
+                    lat64, q64, rounding = self._rounding_bound(live)
+                    if rounding:
+                        polish = (lat64, q64)
+                    else:
+                        lat64.close()
+                        live.best_step = rep.step  # slow, not stalled: look again later
+                if rep.status == lqfire.RUNNING and polish is None:
                     keep.append(live)
                     continue
                 self.batch.remove(live.lat)
-                if self._wants_polish(live, rep):
-                    p, r0 = self._start_polish(live, rep)
+                if polish is not None:
+                    p, r0 = self._start_polish(live, rep, *polish)
                     if r0 is not None:
                         self._retire(p, r0, now, results, polished=True)
                 else:

@@ -188,42 +188,47 @@ def test_destroying_a_member_leaves_its_batch():
         h[0].close()
 
 
-def test_server_polishes_fp32_minima_in_fp64():
-    """An FP32 request whose tolerance lies below the FP32 floor runs in FP32
-    to the floor, then continues from that state in FP64 (a fresh FIRE start,
-    at most polish_steps steps) in the server's second batch: the served
-    result equals that two-stage run done alone, bit for bit.  (The floor is
-    raised here so that the FP32 phase ends within a few dozen steps.)"""
-    say("[serve] FP64 polish from the FP32 minimum")
-    floor = 2.0
-    reqs = _reqs(3, 26, force_tol=1e-7, max_steps=5000)
+def test_server_polishes_stalled_fp32_requests_in_fp64():
+    """An FP32 request that reaches its step limit below the FP32 floor, and
+    whose force the rounding check attributes to rounding, continues from its
+    FP32 state in FP64 (a fresh FIRE start, at most polish_steps steps) in
+    the server's second batch: the served result equals that two-stage run
+    done alone, bit for bit.  (The floor is raised here so that 200 steps end
+    below it, and the check is forced with noise_frac = 0; with the default
+    fraction the check finds the force far above FP32 rounding and reports
+    the requests as capped.)"""
+    say("[serve] FP64 polish of stalled FP32 requests")
+    reqs = _reqs(3, 26, force_tol=1e-7, max_steps=200)
     solo = {}
     for r in reqs:
-        lat = lqfire.lattice_from_config(r, prec="f32")
-        dirs = torch.from_numpy(np.ascontiguousarray(synth.random_directors(r["dir_seed"], lat.N))).cuda()
-        q = lat.set_uniaxial(dirs, lat.empty())
-        v, F = lat.empty(), lat.empty()
-        lat.fire_init(lqfire.fire_params_from_config(r, force_tol=floor), q, v, F)
-        rep = lat.fire_step(5000)
-        assert rep.status == lqfire.CONVERGED
+        lat, q, v, F = _bound(r, "f32")
+        rep = lat.fire_step(200)
+        assert rep.status == lqfire.MAX_STEPS and rep.maxF < 100.0
         lat64 = lqfire.lattice_from_config(r, prec="f64")
         q64 = q.double().contiguous()
         v64, F64 = lat64.empty(), lat64.empty()
         lat64.fire_init(lqfire.fire_params_from_config(r, max_steps=150), q64, v64, F64)
         rep64 = lat64.fire_step(150)
-        solo[r["id"]] = (rep.step, q64.cpu(), rep64.step, rep64.status)
+        solo[r["id"]] = (q64.cpu(), rep64.step, rep64.status)
         lat.close()
         lat64.close()
-    srv = serve.Server(max_members=2, chunk=40, keep_states=True, polish_steps=150, fp32_floor=floor)
+    srv = serve.Server(max_members=2, chunk=40, keep_states=True, polish_steps=150, fp32_floor=100.0,
+                       stall_steps=None, noise_frac=0.0)
     results = srv.run(reqs, realtime=False)
     assert len(results) == 3
     for res in results:
-        steps32, q64, steps, status = solo[res.id]
-        assert res.polished and res.steps == steps32
+        q64, steps, status = solo[res.id]
+        assert res.polished and res.steps == 200
         assert res.polish_steps == steps and res.status == status
         assert torch.equal(srv.states[res.id][0], q64)
     s = serve.summarize(results, srv.wall_s, srv.busy_s)
-    assert s["polished"]["count"] == 3
+    assert s["polished"]["count"] == 3 and srv.noise_checks == 3
+    # after 200 steps from a random start the force is far above FP32
+    # rounding: the check finds no stall and the requests are capped
+    srv = serve.Server(max_members=2, chunk=40, polish_steps=150, fp32_floor=100.0, stall_steps=None)
+    results = srv.run(reqs, realtime=False)
+    assert srv.noise_checks == 3
+    assert all(not r.polished and r.status == lqfire.MAX_STEPS and r.steps == 200 for r in results)
 
 
 def test_server_refuses_a_request_beyond_its_budget():
