@@ -164,7 +164,7 @@ static int64_t resident_blocks(const lq_params& p, int device, bool l23, int wid
 // whose boundary planes cost little more, get the same equal-length cuts in
 // every column, so that neighbouring tiles march the same planes at the same
 // time and share their halo planes in L2 (measured faster than cost-balanced
-// cuts on the 256^3 multi-colloid box).  Larger lattices take 64-plane
+// cuts on the 256^3 multi-colloid box).  Larger lattices take 128-plane
 // chunks, which their many waves balance by themselves (chunk order: at the
 // end of plan_chunks).  Per chunk: whether every
 // site of the padded tile over the whole march is a full bulk site, and per
@@ -216,10 +216,12 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
             cum[(size_t)(c * (nz + 1) + f + 1)] = cum[(size_t)(c * (nz + 1) + f)] + (bulk ? 1.0 : g);
         }
     auto total = [&](int64_t c) { return cum[(size_t)(c * (nz + 1) + nz)]; };
-    // one wave: chunks up to CHUNK_MAX planes, cost-balanced; many waves: 64 planes
+    // one wave: chunks up to CHUNK_MAX planes; many waves: 128 planes (on the
+    // 512^3 patterned wall 3.84 ms per step, against 3.95 with 64 and 3.86
+    // with 256)
     const int64_t zmin = 4;
     const bool one_wave = ncol * ((nz + CHUNK_MAX - 1) / CHUNK_MAX) <= resident;
-    const int64_t zmax = one_wave ? CHUNK_MAX : 64;
+    const int64_t zmax = one_wave ? CHUNK_MAX : 128;
     const int64_t m_lo = (nz + zmax - 1) / zmax;
     const int64_t m_hi = std::max<int64_t>(m_lo, nz / zmin);
     std::vector<int64_t> m((size_t)ncol, m_lo);
@@ -261,11 +263,12 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
                 if (k < mc && !l23) {
                     z1 = nz * k / mc;  // equal plane counts
                 } else if (k < mc) {
-                    // cut where the cost reaches k/mc of the column's, leaving every
-                    // later chunk at least one plane and at most zmax
+                    // cut where the cost reaches k/mc of the column's, keeping this
+                    // and every later chunk within zlo .. zmax planes
                     const double target = total(c) * (double)k / (double)mc;
-                    const int64_t lo_z = std::max(z0 + 1, nz - zmax * (mc - k));
-                    const int64_t hi_z = std::min(z0 + zmax, nz - (mc - k));
+                    const int64_t zlo = std::max<int64_t>(1, std::min<int64_t>(zmin, nz / mc));
+                    const int64_t lo_z = std::max(z0 + zlo, nz - zmax * (mc - k));
+                    const int64_t hi_z = std::min(z0 + zmax, nz - zlo * (mc - k));
                     z1 = lo_z;
                     while (z1 < hi_z && cc[z1] < target) ++z1;
                     if (z1 > lo_z && cc[z1] - target > target - cc[z1 - 1]) --z1;
@@ -476,6 +479,36 @@ int lq_rasterize(const lq_params* p, const lq_object* objs, int32_t n_objs, cons
         anch_site[i] = g.anch_site[i];
         std::memcpy(anch_data + ANCH_STRIDE * i, &g.anch_data[ANCH_STRIDE * i], ANCH_STRIDE * sizeof(double));
     }
+    return LQ_OK;
+}
+
+int lq_step_plan(const lq_params* p, const lq_object* objs, int32_t n_objs, int64_t resident,
+                 int32_t* chunks, uint8_t* bulk, int64_t cap, int64_t* n_chunks, int32_t* tile_nx,
+                 int32_t* tile_ny) {
+    std::string err;
+    int rc = check_params(p, err);
+    if (rc != LQ_OK) return fail(nullptr, rc, err);
+    if (resident <= 0) return fail(nullptr, LQ_EINVAL, "resident must be positive");
+    if (cap < 0 || (cap > 0 && (!chunks || !bulk))) return fail(nullptr, LQ_EINVAL, "bad output arrays");
+    Geometry g;
+    rc = rasterize(*p, bulk_S0(*p), objs, n_objs, nullptr, 0, nullptr, 0, g, err);
+    if (rc != LQ_OK) return fail(nullptr, rc, err);
+    const bool l23 = p->L2 != 0.0 || p->L3 != 0.0 || p->L4 != 0.0;
+    const int wide = tile_wide_for(p->n[0], p->prec, l23);
+    ChunkPlan plan;
+    plan_chunks(*p, l23, wide, g.mask, resident, plan);
+    const int64_t n = (int64_t)plan.chunks.size();
+    for (int64_t i = 0; i < std::min(n, cap); ++i) {
+        const Chunk& c = plan.chunks[(size_t)i];
+        chunks[4 * i + 0] = c.x0;
+        chunks[4 * i + 1] = c.y0;
+        chunks[4 * i + 2] = c.z0;
+        chunks[4 * i + 3] = c.zc;
+        bulk[i] = plan.bulk[(size_t)i];
+    }
+    if (n_chunks) *n_chunks = n;
+    if (tile_nx) *tile_nx = lq::tile_x(p->prec, l23, wide);
+    if (tile_ny) *tile_ny = lq::tile_y(p->prec, l23, wide);
     return LQ_OK;
 }
 
