@@ -731,3 +731,41 @@ def test_director_field_of_a_hedgehog():
     clear = np.abs(S - thr) > 1e-9
     assert np.array_equal(dfc.cpu().numpy().reshape(-1)[clear].astype(bool), (S < thr)[clear])
     assert n_def == int((S < thr).sum()) and n_def > 0
+
+
+def test_full_size_fp64_schedule_matches_stored_oracle():
+    """The 128^3 colloid slab (walls, colloid, L2/L3) at full size on the
+    schedule the oracle ran and stored (tests/golden/colloid_slab128_fire.json:
+    2000 FIRE steps from random directors, then 200 steps from a fresh FIRE
+    start): after each stage the FP64 GPU path takes the same controller
+    decisions, and its energy terms, max|F_i| and q at the 1535 stored sites
+    agree with the oracle's to 1e-10 relative (the FP64 trajectory bound;
+    measured ~1e-13)."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "colloid_slab128_fire.json")
+    with open(path) as f:
+        g = json.load(f)
+    say("[full size] 128^3 slab FP64 against the stored oracle schedule")
+    cfg = synth.colloid_slab(128)
+    lat = lqfire.lattice_from_config(cfg, prec="f64")
+    dirs = to_dev(synth.random_directors(cfg["dir_seed"], lat.N), torch.float64)
+    q = lat.set_uniaxial(dirs, lat.empty())
+    sites = torch.as_tensor(g["sites"], dtype=torch.int64, device="cuda")
+    for stage, steps in (("fire2000", 2000), ("polish200", 200)):
+        v, F = lat.empty(), lat.empty()
+        lat.fire_init(lqfire.fire_params_from_config(cfg, force_tol=0.0, max_steps=steps), q, v, F)
+        rep = lat.fire_step(steps)
+        gs = g["stages"][stage]
+        st = gs["state"]
+        assert (rep.step, rep.n_pos, rep.restarts) == (st["step"], st["n_pos"], st["restarts"])
+        e = lat.energy(q)
+        for k in ("bulk", "elastic", "anchoring", "total"):
+            assert abs(e[k] - gs["energy"][k]) <= 1e-10 * abs(gs["energy"][k]), (stage, k)
+        assert abs(rep.maxF - gs["maxF"]) <= 1e-10 * gs["maxF"]
+        qs = q.reshape(5, -1)[:, sites].T.cpu().numpy()
+        dq = np.abs(qs - np.array(gs["q"])).max()
+        say(f"  {stage}: energy {e['total']:.12e} (oracle {gs['energy']['total']:.12e}), max|dQ| {dq:.2e}")
+        assert dq <= 1e-10 * max(1.0, np.abs(qs).max())
+    lat.close()
