@@ -148,7 +148,7 @@ static int64_t resident_blocks(const lq_params& p, int device, bool l23, int wid
     int n_cu = 0;
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n_cu <= 0)
         n_cu = 256;
-    return (int64_t)n_cu * step_blocks_per_cu(p.prec, l23, wide);
+    return (int64_t)n_cu * step_blocks_per_cu(p.prec, l23, p.L4 != 0.0, wide);
 }
 
 // Work of the step kernels.  A block marches one chunk: a run of planes of
@@ -241,30 +241,18 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
             const int64_t mu = std::min(std::max(m_lo, resident / std::max<int64_t>(ncol, 1)), m_hi);
             for (int64_t c = 0; c < ncol; ++c) m[(size_t)c] = mu;
         }
-        // L2/L3: one more chunk at a time to the column whose chunks cost
-        // most, until the chunks fill one wave of resident blocks (this
-        // minimizes the largest chunk cost for that many chunks)
-        std::priority_queue<std::pair<double, int64_t>> heavy;
-        for (int64_t c = 0; c < ncol; ++c) heavy.push({total(c) / (double)m_lo, c});
-        for (int64_t blocks = ncol * m_lo; one_wave && l23 && blocks < resident && !heavy.empty();) {
-            const int64_t c = heavy.top().second;
-            heavy.pop();
-            if (m[(size_t)c] >= m_hi) continue;
-            ++m[(size_t)c];
-            ++blocks;
-            heavy.push({total(c) / (double)m[(size_t)c], c});
-        }
-        for (int64_t c = 0; c < ncol; ++c) {
-            const int64_t mc = m[(size_t)c];
+        // Cuts of column c into mc chunks: equal plane counts (one-constant
+        // lattices) or equal-cost points (L2/L3), every chunk within
+        // zlo .. zmax planes.
+        auto cuts = [&](int64_t c, int64_t mc) {
+            std::vector<int64_t> z(1, 0);
             const double* cc = &cum[(size_t)(c * (nz + 1))];
-            int64_t z0 = 0;
             for (int64_t k = 1; k <= mc; ++k) {
+                const int64_t z0 = z.back();
                 int64_t z1 = nz;
                 if (k < mc && !l23) {
-                    z1 = nz * k / mc;  // equal plane counts
+                    z1 = nz * k / mc;
                 } else if (k < mc) {
-                    // cut where the cost reaches k/mc of the column's, keeping this
-                    // and every later chunk within zlo .. zmax planes
                     const double target = total(c) * (double)k / (double)mc;
                     const int64_t zlo = std::max<int64_t>(1, std::min<int64_t>(zmin, nz / mc));
                     const int64_t lo_z = std::max(z0 + zlo, nz - zmax * (mc - k));
@@ -273,10 +261,45 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
                     while (z1 < hi_z && cc[z1] < target) ++z1;
                     if (z1 > lo_z && cc[z1] - target > target - cc[z1 - 1]) --z1;
                 }
-                list.push_back({k - 1, Chunk{(int32_t)((c % ntx) * TX), (int32_t)((c / ntx) * TY), (int32_t)z0,
-                                             (int32_t)(z1 - z0)}});
-                z0 = z1;
+                z.push_back(z1);
             }
+            return z;
+        };
+        // Time of one chunk in plane units: its planes (a boundary plane g),
+        // 13% more where the chunk holds any boundary plane (its march reads
+        // masks and anchoring indices for every plane), and two planes for
+        // the halo planes and the pipeline's start (measured on the 128^3
+        // colloid slab, FP32 and FP64).
+        auto chunk_cost = [&](int64_t c, int64_t z0, int64_t z1) {
+            bool all = true;
+            for (int64_t i = z0; i <= z1 + 1 && all; ++i) all = F(c, i);
+            const double* cc = &cum[(size_t)(c * (nz + 1))];
+            return (cc[z1] - cc[z0]) * (all ? 1.0 : 1.13) + 2.0;
+        };
+        auto worst = [&](int64_t c, int64_t mc) {
+            const std::vector<int64_t> z = cuts(c, mc);
+            double w = 0.0;
+            for (size_t k = 1; k < z.size(); ++k) w = std::max(w, chunk_cost(c, z[k - 1], z[k]));
+            return w;
+        };
+        // L2/L3: one more chunk at a time to the column whose costliest chunk
+        // costs most, until the chunks fill one wave of resident blocks
+        std::priority_queue<std::pair<double, int64_t>> heavy;
+        if (one_wave && l23)
+            for (int64_t c = 0; c < ncol; ++c) heavy.push({worst(c, m_lo), c});
+        for (int64_t blocks = ncol * m_lo; one_wave && l23 && blocks < resident && !heavy.empty();) {
+            const int64_t c = heavy.top().second;
+            heavy.pop();
+            if (m[(size_t)c] >= m_hi) continue;
+            ++m[(size_t)c];
+            ++blocks;
+            heavy.push({worst(c, m[(size_t)c]), c});
+        }
+        for (int64_t c = 0; c < ncol; ++c) {
+            const std::vector<int64_t> z = cuts(c, m[(size_t)c]);
+            for (size_t k = 1; k < z.size(); ++k)
+                list.push_back({(int64_t)k - 1, Chunk{(int32_t)((c % ntx) * TX), (int32_t)((c / ntx) * TY),
+                                                      (int32_t)z[k - 1], (int32_t)(z[k] - z[k - 1])}});
         }
     }
     // One wave: by rank within the column, then tile row and column (every

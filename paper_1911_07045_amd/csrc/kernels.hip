@@ -61,24 +61,27 @@ __device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
     }
 }
-// Stores of the streamed fields carry the non-temporal cache policy (bit 1
-// of the buffer instruction's cache-policy operand on gfx950): the next
-// step reads them back from HBM, so they should not displace the reused
-// lines of the current step.
-#ifndef LQ_STORE_POLICY
-#define LQ_STORE_POLICY 2
-#endif
-template <typename T>
-__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v) {
+// Stores of the streamed fields: POL is the buffer instruction's
+// cache-policy operand, 2 (bit 1) the non-temporal policy on gfx950, 0 the
+// default one.
+template <typename T, int POL>
+__device__ __forceinline__ void bst_p(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, T v) {
     if constexpr (sizeof(T) == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff,
-                                              LQ_STORE_POLICY);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, POL);
     } else {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff,
-                                              LQ_STORE_POLICY);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, POL);
     }
 }
+// Cache policy of a step kernel's state stores.  Non-temporal stores keep
+// the written state from displacing lines the step still reuses: measured
+// faster for the one-constant and the FP64 kernels (5% on the 256^3 boxes).
+// The FP32 L2/L3 kernels measured faster with the default policy at every
+// size (14% on the 128^3 bulk box, whose two state buffers fit in the
+// 256 MiB Infinity Cache, 2-4% on the 512^3 patterned wall).  A compile-time
+// choice: a run-time one put a branch in the march loop that cost 1.5%.
+template <typename T, bool L23>
+constexpr int store_policy() { return (L23 && sizeof(T) == 4) ? 0 : 2; }
 
 // Barrier for data exchanged through LDS only: waits for this wave's LDS
 // operations, not for its global loads and stores (which __syncthreads()
@@ -281,6 +284,16 @@ __device__ __forceinline__ void unit(int k, int s, int& dx, int& dy, int& dz) {
     dz = k == 2 ? s : 0;
 }
 
+// The FP32 L2/L3 kernels evaluate boundary sites branch-free: every stencil
+// position holds a finite value (0 where no simulated site is), so a term
+// whose coefficient is 0 adds exactly nothing, and the LDS reads of all
+// terms can be in flight together (the branch per term serialized them on
+// LDS latency; measured 33% faster on the 128^3 colloid slab).  In FP64 the
+// branch-free form needs more registers than the kernel has and measured
+// slower, so the FP64 kernels read only the terms that are present.
+template <typename T>
+constexpr bool branch_free() { return sizeof(T) == 4; }
+
 // mean differences C_k (k != skip) at offset o of the stencil
 template <typename T, bool L23, bool BULK, int W>
 __device__ __forceinline__ void mean_diffs(const Stencil<T, L23, BULK, W>& P, int ox, int oy, int oz,
@@ -299,8 +312,8 @@ __device__ __forceinline__ void mean_diffs(const Stencil<T, L23, BULK, W>& P, in
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             T v = a0 * P.at(ox, oy, oz, c);
-            if (ap != T(0)) v = fma_t(ap, P.at(ox + ex, oy + ey, oz + ez, c), v);
-            if (am != T(0)) v = fma_t(am, P.at(ox - ex, oy - ey, oz - ez, c), v);
+            if (branch_free<T>() || ap != T(0)) v = fma_t(ap, P.at(ox + ex, oy + ey, oz + ez, c), v);
+            if (branch_free<T>() || am != T(0)) v = fma_t(am, P.at(ox - ex, oy - ey, oz - ez, c), v);
             Ck[k][c] = v;
         }
     }
@@ -347,7 +360,7 @@ __device__ __forceinline__ void anch_load(const LatDev& L, int arow1, AnchRow<T>
 // loaded ahead by the caller) or row arow1 - 1 of the FP64 forms, read here
 // (narrow tiles: on the serving stream of small boxes this measured a lower
 // tail latency than the early loads).
-template <typename T, bool L23, bool BULK, int W>
+template <typename T, bool L23, bool L4, bool BULK, int W>
 __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, uint32_t m0,
                                            const LatDev& L, const AnchRow<T>& AR, int arow1, T F[5]) {
     const T A = T(L.A), B = T(L.B), C = T(L.C), L1 = T(L.L1);
@@ -414,16 +427,19 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
             for (int c = 0; c < 5; ++c) g[c] = fma_t(L23s, fma_t(T(-0.25), X[c], col[c]), g[c]);
         }
     } else {
-        // bond sums: L1 and the same-axis part of L2/L3
+        // bond sums: L1 and the same-axis part of L2/L3.  Branch-free (FP32
+        // L2/L3): an absent bond gets weight 0; the other kernels skip it.
+        constexpr bool BF = L23 && branch_free<T>();
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
             for (int s = -1; s <= 1; s += 2) {
-                if (!has_nb(m0, k, s)) continue;
+                if (!BF && !has_nb(m0, k, s)) continue;
                 int dx, dy, dz;
                 unit(k, s, dx, dy, dz);
                 uint32_t mn = P.mask(dx, dy, dz);
                 T w = (n_choices(m0, k) == 2 ? T(0.5) : T(1)) + (n_choices(mn, k) == 2 ? T(0.5) : T(1));
+                w = has_nb(m0, k, s) ? w : T(0);
                 T d[5], o[5];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) d[c] = q0[c] - P.at(dx, dy, dz, c);
@@ -437,11 +453,17 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
 #pragma unroll
                     for (int c = 0; c < 5; ++c) g[c] = fma_t(wl23, o[c], g[c]);
                 }
+                // one bond's reads at a time in flight: hoisting every
+                // stencil read of the branch-free form spills registers
+                if (BF) __builtin_amdgcn_sched_barrier(0);
             }
     }
     if (L23 && !BULK) {
         const T L2 = T(L.L2), L3 = T(L.L3);
-        // cross-axis part: every site x whose mean difference C_j contains Q(centre)
+        // cross-axis part: every site x whose mean difference C_j contains
+        // Q(centre).  The branch per site x also keeps the branch-free form
+        // to one mean-difference evaluation's reads in flight at a time
+        // (without it every read of all seven is hoisted and registers spill).
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
 #pragma unroll
@@ -452,7 +474,7 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
                 uint32_t mx = P.mask(dx, dy, dz);
                 T ap, a0, am;
                 mean_diff_coef(mx, j, ap, a0, am);
-                T coef = s > 0 ? ap : am;
+                const T coef = s > 0 ? ap : am;
                 if (coef == T(0)) continue;
                 T Ck[3][5], h[5];
                 mean_diffs(P, dx, dy, dz, j, mx, Ck);
@@ -471,7 +493,7 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
             }
         }
     }
-    if (L23) {
+    if (L4) {
         if (L.L4 != 0.0) {
             // chiral term: the site's own tensor, then every C_k(x) holding Q(centre)
             const T hL4 = T(0.5 * L.L4);
@@ -701,7 +723,7 @@ __device__ __forceinline__ bool bulk_plane_of(const PlaneBits& b, int f) {
 #endif
 static_assert(LQ_PREFETCH == 1 || LQ_PREFETCH == 2, "prefetch depth is 1 or 2 planes");
 
-template <typename T, bool L23, int MODE, bool BULK, int W>
+template <typename T, bool L23, bool L4, int MODE, bool BULK, int W>
 __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_in,
                                       const T* __restrict__ v_in, const T* __restrict__ F_in,
                                       T* __restrict__ q_out, T* __restrict__ v_out,
@@ -716,6 +738,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
     constexpr int RING_ITEMS = G::RING_ITEMS, ITEMS_PER_THREAD = G::IPT;
     constexpr bool STEP = MODE != MODE_FORCE;
     constexpr bool USES_V = MODE == MODE_FIRE || MODE == MODE_NAG;
+    constexpr bool ZERO_SOLID = !BULK && L23 && branch_free<T>();
     const int64_t N = L.N;
     const int nxy = L.nx * L.ny;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
@@ -780,7 +803,9 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
             R.iq[j] = bld<T>(rq_in, offj, 0u);
             if (USES_V) R.iv[j] = bld<T>(rv_in, offj, 0u);
             if (STEP) R.iF[j] = bld<T>(rF_in, offj, 0u);
-            if (!BULK) R.im[j] = __builtin_amdgcn_raw_buffer_load_b8(rmask, (int)(okj && it_c[j] == 0 ? t : NONE), 0, 0);
+            // the branch-free kernels zero the sites that are not simulated,
+            // so they need the mask of every ring item
+            if (!BULK) R.im[j] = __builtin_amdgcn_raw_buffer_load_b8(rmask, (int)(okj && (ZERO_SOLID || it_c[j] == 0) ? t : NONE), 0, 0);
         }
     };
     // drift the registers into LDS slot; returns the own site's q' and v1
@@ -807,6 +832,9 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                 v1[c] = T(0);
                 x = qn[c];
             }
+            // branch-free kernels: a site that is not simulated holds 0 in
+            // LDS, whatever its stored tensor (the force reads it with weight 0)
+            if (ZERO_SOLID) x = (R.m & M_SIM) ? x : T(0);
             sq[slot][c][ty + 1][tx + 1] = x;
         }
         m = BULK ? (uint32_t)M_FULL : R.m;
@@ -824,6 +852,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
                 const T mj = fma_t(cv, R.iv[j], dt * R.iF[j]);
                 x = fma_t(cv, mj, x + mj);
             }
+            if (ZERO_SOLID) x = (R.im[j] & M_SIM) ? x : T(0);
             sq[slot][it_c[j]][it_py[j]][it_px[j]] = x;
             if (!BULK && it_c[j] == 0) sm[slot][it_py[j]][it_px[j]] = (uint8_t)R.im[j];
         }
@@ -901,39 +930,49 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
             // a plane whose 3 x 3 x 3 neighbourhoods are all full bulk sites
             // takes the bulk evaluation also inside a boundary tile (wide
             // tiles only: the narrow ones serve small boxes, where few planes
-            // qualify and the extra code costs registers)
-            if (W == 1 && !BULK && bulk_plane_of(plane_bulk, f)) {
+            // qualify and the extra code costs registers).  The first two
+            // iterations have no plane of the chunk to evaluate (their stores
+            // are dropped): the L2/L3 kernels compute no force there (in the
+            // one-constant kernels the branch split the loop body and measured
+            // 3% slower than the two wasted evaluations).
+            if (L23 && !in_chunk) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) F[c] = T(0);
+            } else if (W == 1 && !BULK && bulk_plane_of(plane_bulk, f)) {
                 Stencil<T, L23, true, W> PB;
                 PB.q = sq; PB.m = sm;
                 PB.s[0] = P.s[0]; PB.s[1] = P.s[1]; PB.s[2] = P.s[2];
                 PB.cx = P.cx; PB.cy = P.cy;
-                site_force<T, L23, true, W>(PB, (uint32_t)M_FULL, L, A, 0, F);
+                site_force<T, L23, L4, true, W>(PB, (uint32_t)M_FULL, L, A, 0, F);
             } else {
-                site_force<T, L23, BULK, W>(P, m_older, L, A, a_older, F);
+                site_force<T, L23, L4, BULK, W>(P, m_older, L, A, a_older, F);
             }
-    #pragma unroll
-            for (int c = 0; c < 5; ++c) {
-                const T Fc = live ? F[c] : T(0);
-                if (MODE == MODE_FIRE || MODE == MODE_NAG) {
-                    const T v2 = live ? (MODE == MODE_FIRE ? fma_t(hdt, F[c], v1_older[c]) : v1_older[c]) : T(0);
-                    const T qc = live ? (MODE == MODE_FIRE ? P.at(0, 0, 0, c) : q_older[c]) : T(0);
-                    bst<T>(rq_out, off, c * cs, qc);
-                    bst<T>(rv_out, off, c * cs, v2);
-                    bst<T>(rF_out, off, c * cs, Fc);
-                    const double fd = (double)Fc, vd = (double)v2;
-                    red[0] = fma(fd, vd, red[0]);
-                    red[1] = fma(fd, fd, red[1]);
-                    red[2] = fma(vd, vd, red[2]);
-                    fmax_abs = fmax(fmax_abs, fabs(Fc));
-                } else if (MODE == MODE_GD) {
-                    const T qc = live ? P.at(0, 0, 0, c) : T(0);
-                    bst<T>(rq_out, off, c * cs, qc);
-                    bst<T>(rF_out, off, c * cs, Fc);
-                    const double fd = (double)Fc;
-                    red[1] = fma(fd, fd, red[1]);
-                    fmax_abs = fmax(fmax_abs, fabs(Fc));
-                } else {
-                    bst<T>(rF_out, off, c * cs, Fc);
+            {
+                constexpr int POL = store_policy<T, L23>();
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    const T Fc = live ? F[c] : T(0);
+                    if (MODE == MODE_FIRE || MODE == MODE_NAG) {
+                        const T v2 = live ? (MODE == MODE_FIRE ? fma_t(hdt, F[c], v1_older[c]) : v1_older[c]) : T(0);
+                        const T qc = live ? (MODE == MODE_FIRE ? P.at(0, 0, 0, c) : q_older[c]) : T(0);
+                        bst_p<T, POL>(rq_out, off, c * cs, qc);
+                        bst_p<T, POL>(rv_out, off, c * cs, v2);
+                        bst_p<T, POL>(rF_out, off, c * cs, Fc);
+                        const double fd = (double)Fc, vd = (double)v2;
+                        red[0] = fma(fd, vd, red[0]);
+                        red[1] = fma(fd, fd, red[1]);
+                        red[2] = fma(vd, vd, red[2]);
+                        fmax_abs = fmax(fmax_abs, fabs(Fc));
+                    } else if (MODE == MODE_GD) {
+                        const T qc = live ? P.at(0, 0, 0, c) : T(0);
+                        bst_p<T, POL>(rq_out, off, c * cs, qc);
+                        bst_p<T, POL>(rF_out, off, c * cs, Fc);
+                        const double fd = (double)Fc;
+                        red[1] = fma(fd, fd, red[1]);
+                        fmax_abs = fmax(fmax_abs, fabs(Fc));
+                    } else {
+                        bst_p<T, POL>(rF_out, off, c * cs, Fc);
+                    }
                 }
             }
         }
@@ -944,9 +983,9 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
     __builtin_amdgcn_sched_barrier(0);  // keep the dropped stores behind the loads
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        bst<T>(rF_out, NONE, c * cs, T(0));
-        if (STEP) bst<T>(rq_out, NONE, c * cs, T(0));
-        if (USES_V) bst<T>(rv_out, NONE, c * cs, T(0));
+        bst_p<T, 2>(rF_out, NONE, c * cs, T(0));
+        if (STEP) bst_p<T, 2>(rq_out, NONE, c * cs, T(0));
+        if (USES_V) bst_p<T, 2>(rv_out, NONE, c * cs, T(0));
     }
     __builtin_amdgcn_sched_barrier(0);
     if (PF == 1) {
@@ -965,7 +1004,7 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
 // One block of the force / FIRE step: tile `bid` of lattice L.  `nblocks`
 // is the lattice's own tile count; partials are indexed by tile, so the
 // reduction order does not depend on how blocks are dispatched.
-template <typename T, bool L23, int MODE, int W>
+template <typename T, bool L23, bool L4, int MODE, int W>
 __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, const T* __restrict__ qin,
                                            T* __restrict__ Fout, double* partials, FireDev* st,
                                            int nblocks, int bid) {
@@ -1003,24 +1042,26 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
         PlaneBits all;
 #pragma unroll
         for (int i = 0; i < PLANE_WORDS; ++i) all.w[i] = ~(uint64_t)0;
-        march<T, L23, MODE, true, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
+        march<T, L23, L4, MODE, true, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
                                   sq, sm, red, all);
     } else {
-        march<T, L23, MODE, false, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
+        march<T, L23, L4, MODE, false, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
                                    sq, sm, red, L.tile_planes[bid]);
     }
     if (STEP) grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
 }
 
-template <typename T, bool L23, int MODE, int W>
-__global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_per_eu(Tile<T, L23, W>::WAVES))) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
+// L4: the kernel evaluates the chiral term (a kernel of its own, so that the
+// common L2/L3 kernels do not carry its registers).
+template <typename T, bool L23, bool L4, int MODE, int W>
+__global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_per_eu(L4 ? 1 : Tile<T, L23, W>::WAVES))) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
                                                     T* __restrict__ Fout, double* partials,
                                                     FireDev* st) {
     const int nblocks = (int)gridDim.x;
     int bid = (int)blockIdx.x;
     // keep neighbouring tiles on one XCD: dispatch is round-robin over 8 XCDs
     if ((nblocks & 7) == 0) bid = (bid & 7) * (nblocks >> 3) + (bid >> 3);
-    step_block<T, L23, MODE, W>(L, b, qin, Fout, partials, st, nblocks, bid);
+    step_block<T, L23, L4, MODE, W>(L, b, qin, Fout, partials, st, nblocks, bid);
 }
 
 // ---------------------------------------------------------------------------
@@ -1048,7 +1089,7 @@ __global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_p
         b.q[i] = (T*)M.q[i]; b.v[i] = (T*)M.v[i]; b.F[i] = (T*)M.F[i];
     }
     const LatDev& L = M.L;
-    step_block<T, L23, MODE_FIRE, W>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
+    step_block<T, L23, L23, MODE_FIRE, W>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
                              (int)blockIdx.x - off[m]);
 }
 
@@ -1418,19 +1459,21 @@ static int hip_status(hipError_t e) { return e == hipSuccess ? LQ_OK : LQ_EHIP; 
 int64_t n_step_blocks(const LatDev& L) { return L.nchunks; }
 
 // Resident blocks per compute unit of the fused FIRE step kernel.
-template <typename T, bool L23, int W>
+template <typename T, bool L23, bool L4, int W>
 static int blocks_per_cu() {
     int n = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<T, L23, MODE_FIRE, W>, Tile<T, L23, W>::N, 0);
+    hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<T, L23, L4, MODE_FIRE, W>, Tile<T, L23, W>::N, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
-int step_blocks_per_cu(int prec, bool l23, int wide) {
-    if (prec == LQ_F64) {
-        if (l23) return wide ? blocks_per_cu<double, true, 1>() : blocks_per_cu<double, true, 0>();
-        return wide ? blocks_per_cu<double, false, 1>() : blocks_per_cu<double, false, 0>();
-    }
-    if (l23) return wide ? blocks_per_cu<float, true, 1>() : blocks_per_cu<float, true, 0>();
-    return wide ? blocks_per_cu<float, false, 1>() : blocks_per_cu<float, false, 0>();
+template <typename T>
+static int blocks_per_cu_t(bool l23, bool l4, int wide) {
+    if (!l23) return wide ? blocks_per_cu<T, false, false, 1>() : blocks_per_cu<T, false, false, 0>();
+    if (l4) return wide ? blocks_per_cu<T, true, true, 1>() : blocks_per_cu<T, true, true, 0>();
+    return wide ? blocks_per_cu<T, true, false, 1>() : blocks_per_cu<T, true, false, 0>();
+}
+int step_blocks_per_cu(int prec, bool l23, bool l4, int wide) {
+    return prec == LQ_F64 ? blocks_per_cu_t<double>(l23, l4, wide) : blocks_per_cu_t<float>(l23, l4, wide);
 }
 
 int64_t n_energy_blocks(const LatDev& L) {
@@ -1447,10 +1490,12 @@ template <typename T, int MODE, int W>
 static void launch_march(const LatDev& L, bool l23, const Bufs<T>& b, const void* q, void* F, double* partials,
                          FireDev* st, hipStream_t s) {
     const dim3 g((unsigned)n_step_blocks(L));
-    if (l23)
-        k_march<T, true, MODE, W><<<g, Tile<T, true, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st);
+    if (l23 && L.L4 != 0.0)
+        k_march<T, true, true, MODE, W><<<g, Tile<T, true, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st);
+    else if (l23)
+        k_march<T, true, false, MODE, W><<<g, Tile<T, true, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st);
     else
-        k_march<T, false, MODE, W><<<g, Tile<T, false, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st);
+        k_march<T, false, false, MODE, W><<<g, Tile<T, false, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st);
 }
 
 template <typename T, int MODE>

@@ -75,6 +75,9 @@ int rasterize(const lq_params& p, double S0, const lq_object* objs, int32_t n_ob
 #ifndef LQ_TILE_Y_F64_L23
 #define LQ_TILE_Y_F64_L23 4
 #endif
+#ifndef LQ_WAVES_F64_L23
+#define LQ_WAVES_F64_L23 1
+#endif
 template <int TX_, int TY_, int WAVES_>
 struct TileGeom {
     static constexpr int X = TX_, Y = TY_;
@@ -95,7 +98,7 @@ struct Tile<float, true, 1> : TileGeom<LQ_TILE_X_F32_L23, LQ_TILE_Y_F32_L23, 1> 
 template <>
 struct Tile<double, false, 1> : TileGeom<LQ_TILE_X_F64, LQ_TILE_Y_F64, 1> {};
 template <>
-struct Tile<double, true, 1> : TileGeom<LQ_TILE_X_F64_L23, LQ_TILE_Y_F64_L23, 1> {};
+struct Tile<double, true, 1> : TileGeom<LQ_TILE_X_F64_L23, LQ_TILE_Y_F64_L23, LQ_WAVES_F64_L23> {};
 template <bool L23>
 struct Tile<float, L23, 0> : TileGeom<64, 8, Tile<float, L23, 1>::WAVES> {};
 template <bool L23>
@@ -215,7 +218,7 @@ int launch_batch_steps(int prec, bool l23, const MemberDev* mem, int n_narrow, c
                        int tiles_narrow, int n_wide, const int* tile_off_wide, int tiles_wide,
                        const int* fin_off, int total_fin, FireDev* gather, int64_t n_steps, void* stream);
 int64_t n_step_blocks(const LatDev& L);
-int step_blocks_per_cu(int prec, bool l23, int wide);
+int step_blocks_per_cu(int prec, bool l23, bool l4, int wide);
 int64_t n_energy_blocks(const LatDev& L);
 
 }  // namespace lq
