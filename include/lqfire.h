@@ -350,16 +350,19 @@ int lq_batch_step(lq_batch* b, int64_t n_steps, lq_fire_report* reports);
  * blocks for a lattice with the given parameters and objects (as
  * lq_set_boundaries would rasterize them, without records or extra object
  * sites) on a device that keeps `resident` step blocks resident at once
- * (> 0).  Each block marches one chunk: the X x Y column tile whose first
- * site is (x0, y0), over the planes z0 .. z0 + zc - 1.  Writes up to cap
- * chunks as 4 int32 each {x0, y0, z0, zc} into chunks and one byte each
- * into bulk (1: every site of the tile, its one-site ring and the planes
- * z0 - 1 and z0 + zc is simulated with all six neighbours), in launch order;
- * *n_chunks receives the full count, *tile_nx and *tile_ny the tile size.
- * Needs no GPU.  LQ_EINVAL on bad parameters, objects or resident <= 0. */
+ * (> 0).  A chunk is the X x Y column tile whose first site is (x0, y0), over
+ * the planes z0 .. z0 + zc - 1; a block marches one chunk, or two one after
+ * the other.  Writes up to cap chunks as 4 int32 each {x0, y0, z0, zc} into
+ * chunks, one byte each into bulk (1: every site of the tile, its one-site
+ * ring and the planes z0 - 1 and z0 + zc is simulated with all six
+ * neighbours) and, if block is not NULL, the index of the block that marches
+ * it into block, in launch order (blocks in order, a block's chunks in the
+ * order it marches them); *n_chunks receives the full count, *tile_nx and
+ * *tile_ny the tile size.  Needs no GPU.  LQ_EINVAL on bad parameters,
+ * objects or resident <= 0. */
 int lq_step_plan(const lq_params* p, const lq_object* objs, int32_t n_objs, int64_t resident,
-                 int32_t* chunks, uint8_t* bulk, int64_t cap, int64_t* n_chunks, int32_t* tile_nx,
-                 int32_t* tile_ny);
+                 int32_t* chunks, uint8_t* bulk, int32_t* block, int64_t cap, int64_t* n_chunks,
+                 int32_t* tile_nx, int32_t* tile_ny);
 
 /* ---- streaming ceiling (measurement helper) ----
  * A FIRE step (Algorithm 1) reads q, v, F and writes them back: 15 streams in

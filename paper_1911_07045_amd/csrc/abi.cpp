@@ -36,6 +36,7 @@ struct lq_lattice {
     uint8_t* d_tile = nullptr;
     PlaneBits* d_tile_planes = nullptr;
     Chunk* d_chunks = nullptr;
+    int32_t* d_first = nullptr;
     int32_t* d_anch_index = nullptr;
     double* d_anch_data = nullptr;
     void* d_anch_force = nullptr;  // K upper triangle and b of each row, in the field's element type
@@ -174,6 +175,7 @@ struct ChunkPlan {
     std::vector<Chunk> chunks;
     std::vector<uint8_t> bulk;
     std::vector<PlaneBits> planes;
+    std::vector<int32_t> first;  // block b marches chunks first[b] .. first[b + 1] - 1
 };
 
 static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vector<uint8_t>& mask,
@@ -207,7 +209,10 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
         }
     }
     auto F = [&](int64_t c, int64_t i) { return full[(size_t)(c * P + i)] != 0; };
-    // cum[c][f]: cost of planes 0 .. f - 1 of column c
+    // cum[c][f]: cost of planes 0 .. f - 1 of column c, a boundary plane
+    // costing g bulk planes (2.2 for the FP32 kernels, which evaluate
+    // boundary planes branch-free, measured 1.5% slower on the 128^3 colloid
+    // slab and the 512^3 patterned wall than 3)
     const double g = 3.0;
     std::vector<double> cum((size_t)(ncol * (nz + 1)), 0.0);
     for (int64_t c = 0; c < ncol; ++c)
@@ -216,6 +221,11 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
             cum[(size_t)(c * (nz + 1) + f + 1)] = cum[(size_t)(c * (nz + 1) + f)] + (bulk ? 1.0 : g);
         }
     auto total = [&](int64_t c) { return cum[(size_t)(c * (nz + 1) + nz)]; };
+    // nonfull[c][i]: padded planes 0 .. i - 1 of column c that are not all M_FULL
+    std::vector<int64_t> nonfull((size_t)(ncol * (P + 1)), 0);
+    for (int64_t c = 0; c < ncol; ++c)
+        for (int64_t i = 0; i < P; ++i)
+            nonfull[(size_t)(c * (P + 1) + i + 1)] = nonfull[(size_t)(c * (P + 1) + i)] + (F(c, i) ? 0 : 1);
     // one wave: chunks up to CHUNK_MAX planes; many waves: 128 planes (on the
     // 512^3 patterned wall 3.84 ms per step, against 3.95 with 64 and 3.86
     // with 256)
@@ -228,6 +238,8 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
     const char* env = std::getenv("LQ_ZC");
     const int zfix = env ? std::atoi(env) : 0;
     std::vector<std::pair<int64_t, Chunk>> list;  // (rank within the column, chunk)
+    typedef std::vector<std::pair<int64_t, Chunk>> Block;
+    std::vector<Block> packed;  // non-empty: the blocks of a packed plan
     if (zfix >= 1 && zfix <= CHUNK_MAX) {
         for (int64_t c = 0; c < ncol; ++c)
             for (int64_t z0 = 0, k = 0; z0 < nz; z0 += zfix, ++k)
@@ -271,8 +283,8 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
         // the halo planes and the pipeline's start (measured on the 128^3
         // colloid slab, FP32 and FP64).
         auto chunk_cost = [&](int64_t c, int64_t z0, int64_t z1) {
-            bool all = true;
-            for (int64_t i = z0; i <= z1 + 1 && all; ++i) all = F(c, i);
+            const int64_t* nf = &nonfull[(size_t)(c * (P + 1))];
+            const bool all = nf[z1 + 2] - nf[z0] == 0;
             const double* cc = &cum[(size_t)(c * (nz + 1))];
             return (cc[z1] - cc[z0]) * (all ? 1.0 : 1.13) + 2.0;
         };
@@ -295,11 +307,57 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
             ++blocks;
             heavy.push({worst(c, m[(size_t)c]), c});
         }
+        double worst_chunk = 0.0;
         for (int64_t c = 0; c < ncol; ++c) {
             const std::vector<int64_t> z = cuts(c, m[(size_t)c]);
-            for (size_t k = 1; k < z.size(); ++k)
+            for (size_t k = 1; k < z.size(); ++k) {
                 list.push_back({(int64_t)k - 1, Chunk{(int32_t)((c % ntx) * TX), (int32_t)((c / ntx) * TY),
                                                       (int32_t)z[k - 1], (int32_t)(z[k] - z[k - 1])}});
+                worst_chunk = std::max(worst_chunk, chunk_cost(c, z[k - 1], z[k]));
+            }
+        }
+        // Packed plan (one wave, FP64 L2/L3; the step kernels of the other
+        // plans march one chunk per block): with few columns per resident
+        // block (64 FP64 columns of the 128^3 slab for 256 blocks) whole
+        // chunks per column cannot balance the columns' costs.  Each column is cut from
+        // the bottom into chunks of cost at most M, the chunks are paired
+        // largest with smallest while a pair stays within M, and a block
+        // marches its pair one chunk after the other; M is the least value
+        // (bisection) whose blocks fit in one wave.  Taken when it lowers the
+        // costliest block by 3% or more.
+        auto pack = [&](double M, std::vector<Block>& blk) {
+            blk.clear();
+            std::vector<std::pair<double, std::pair<int64_t, Chunk>>> pieces;
+            for (int64_t c = 0; c < ncol; ++c) {
+                for (int64_t z0 = 0, k = 0; z0 < nz; ++k) {
+                    int64_t z1 = std::min(nz, z0 + zmin);
+                    while (z1 < nz && z1 - z0 < zmax && chunk_cost(c, z0, z1 + 1) <= M) ++z1;
+                    // no last chunk below zmin planes
+                    if (z1 < nz && nz - z1 < zmin) z1 = nz - z0 >= 2 * zmin ? nz - zmin : nz;
+                    pieces.push_back({chunk_cost(c, z0, z1),
+                                      {k, Chunk{(int32_t)((c % ntx) * TX), (int32_t)((c / ntx) * TY), (int32_t)z0,
+                                                (int32_t)(z1 - z0)}}});
+                    z0 = z1;
+                }
+            }
+            std::stable_sort(pieces.begin(), pieces.end(),
+                             [](const std::pair<double, std::pair<int64_t, Chunk>>& a,
+                                const std::pair<double, std::pair<int64_t, Chunk>>& b) { return a.first > b.first; });
+            for (size_t i = 0, j = pieces.size(); i < j; ++i) {
+                blk.push_back(Block(1, pieces[i].second));
+                if (j - 1 > i && pieces[i].first + pieces[j - 1].first <= M) blk.back().push_back(pieces[--j].second);
+            }
+            return (int64_t)blk.size();
+        };
+        if (one_wave && l23 && p.prec == LQ_F64 && zfix == 0) {
+            std::vector<Block> trial;
+            double lo = 0.0, hi = worst_chunk;
+            for (int it = 0; it < 40; ++it) {
+                const double M = 0.5 * (lo + hi);
+                if (pack(M, trial) <= resident) hi = M;
+                else lo = M;
+            }
+            if (hi < 0.97 * worst_chunk && pack(hi, trial) <= resident) packed.swap(trial);
         }
     }
     // One wave: by rank within the column, then tile row and column (every
@@ -310,18 +368,27 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
     // gets its share of the heavier wall chunks (by rank alone, the first and
     // last eighths held all of them), and neighbouring columns still march
     // the same planes together.
+    // A block marches one chunk, or (packed plans) two chunks one after the
+    // other; it is ordered by its first chunk.
+    typedef std::vector<std::pair<int64_t, Chunk>> Block;
+    std::vector<Block> blocks;
+    for (const auto& e : list) blocks.push_back(Block(1, e));
+    if (!packed.empty()) blocks.swap(packed);
     const int64_t gsize = one_wave ? ncol : (ncol + 7) / 8;
-    std::stable_sort(list.begin(), list.end(),
-                     [&](const std::pair<int64_t, Chunk>& a, const std::pair<int64_t, Chunk>& b) {
-                         const int64_t ca = a.second.x0 / TX + ntx * (a.second.y0 / TY);
-                         const int64_t cb = b.second.x0 / TX + ntx * (b.second.y0 / TY);
-                         if (ca / gsize != cb / gsize) return ca / gsize < cb / gsize;
-                         return a.first < b.first;
-                     });
+    std::stable_sort(blocks.begin(), blocks.end(), [&](const Block& A, const Block& B) {
+        const std::pair<int64_t, Chunk>& a = A.front();
+        const std::pair<int64_t, Chunk>& b = B.front();
+        const int64_t ca = a.second.x0 / TX + ntx * (a.second.y0 / TY);
+        const int64_t cb = b.second.x0 / TX + ntx * (b.second.y0 / TY);
+        if (ca / gsize != cb / gsize) return ca / gsize < cb / gsize;
+        return a.first < b.first;
+    });
     out.chunks.clear();
     out.bulk.clear();
     out.planes.clear();
-    for (const auto& e : list) {
+    out.first.assign(1, 0);
+    for (const Block& blk : blocks) {
+      for (const auto& e : blk) {
         const Chunk& ch = e.second;
         const int64_t c = ch.x0 / TX + ntx * (ch.y0 / TY);
         bool all = true;
@@ -333,6 +400,8 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
         out.chunks.push_back(ch);
         out.bulk.push_back(all ? 1 : 0);
         out.planes.push_back(bits);
+      }
+      out.first.push_back((int32_t)out.chunks.size());
     }
 }
 
@@ -341,6 +410,7 @@ static void free_geometry(lq_lattice* lat) {
     if (lat->d_tile) (void)hipFree(lat->d_tile);
     if (lat->d_tile_planes) (void)hipFree(lat->d_tile_planes);
     if (lat->d_chunks) (void)hipFree(lat->d_chunks);
+    if (lat->d_first) (void)hipFree(lat->d_first);
     if (lat->d_anch_index) (void)hipFree(lat->d_anch_index);
     if (lat->d_anch_data) (void)hipFree(lat->d_anch_data);
     if (lat->d_anch_force) (void)hipFree(lat->d_anch_force);
@@ -350,6 +420,7 @@ static void free_geometry(lq_lattice* lat) {
     lat->d_anch_data = nullptr;
     lat->d_anch_force = nullptr;
     lat->d_chunks = nullptr;
+    lat->d_first = nullptr;
 }
 
 // Uploads a rasterized geometry and refreshes the device view.
@@ -367,6 +438,10 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     ChunkPlan plan;
     plan_chunks(p, lat->l23, d.wide, g.mask, resident_blocks(p, lat->device, lat->l23, d.wide), plan);
     d.nchunks = (int)plan.chunks.size();
+    d.nblocks = (int)plan.first.size() - 1;
+    HIPCHK(lat, hipMalloc(&lat->d_first, plan.first.size() * sizeof(int32_t)));
+    HIPCHK(lat, hipMemcpy(lat->d_first, plan.first.data(), plan.first.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
     const std::vector<uint8_t>& tiles = plan.bulk;
     const std::vector<PlaneBits>& tile_planes = plan.planes;
     HIPCHK(lat, hipMalloc(&lat->d_chunks, plan.chunks.size() * sizeof(Chunk)));
@@ -409,6 +484,7 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     }
     d.mask = lat->d_mask;
     d.chunks = lat->d_chunks;
+    d.first = lat->d_first;
     d.tile_bulk = lat->d_tile;
     d.tile_planes = lat->d_tile_planes;
     d.n_anch = lat->n_anch;
@@ -506,8 +582,8 @@ int lq_rasterize(const lq_params* p, const lq_object* objs, int32_t n_objs, cons
 }
 
 int lq_step_plan(const lq_params* p, const lq_object* objs, int32_t n_objs, int64_t resident,
-                 int32_t* chunks, uint8_t* bulk, int64_t cap, int64_t* n_chunks, int32_t* tile_nx,
-                 int32_t* tile_ny) {
+                 int32_t* chunks, uint8_t* bulk, int32_t* block, int64_t cap, int64_t* n_chunks,
+                 int32_t* tile_nx, int32_t* tile_ny) {
     std::string err;
     int rc = check_params(p, err);
     if (rc != LQ_OK) return fail(nullptr, rc, err);
@@ -529,6 +605,9 @@ int lq_step_plan(const lq_params* p, const lq_object* objs, int32_t n_objs, int6
         chunks[4 * i + 3] = c.zc;
         bulk[i] = plan.bulk[(size_t)i];
     }
+    if (block)
+        for (size_t b = 0; b + 1 < plan.first.size(); ++b)
+            for (int32_t i = plan.first[b]; i < plan.first[b + 1] && (int64_t)i < cap; ++i) block[i] = (int32_t)b;
     if (n_chunks) *n_chunks = n;
     if (tile_nx) *tile_nx = lq::tile_x(p->prec, l23, wide);
     if (tile_ny) *tile_ny = lq::tile_y(p->prec, l23, wide);

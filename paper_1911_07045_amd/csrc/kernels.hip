@@ -1016,9 +1016,6 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
     __shared__ double scratch[G::N / 64][4];
     __shared__ int last_flag;
 
-    const Chunk ch = L.chunks[bid];
-    const int x0 = ch.x0, y0 = ch.y0, z0 = ch.z0, zc = ch.zc;
-
     constexpr bool STEP = MODE != MODE_FORCE;
     const T *q_in, *v_in = nullptr, *F_in = nullptr;
     T *q_out = nullptr, *v_out = nullptr, *F_out;
@@ -1038,15 +1035,25 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
         F_out = Fout;
     }
     double red[4] = {0.0, 0.0, 0.0, 0.0};
-    if (L.tile_bulk[bid]) {
-        PlaneBits all;
+    // the block's chunks one after the other: a packed plan (FP64 L2/L3 only)
+    // gives some blocks two; every other plan one per block, chunk bid (the
+    // loop costs the other kernels registers)
+    constexpr bool PACKED = L23 && sizeof(T) == 8;
+    const int i0 = PACKED ? L.first[bid] : bid, i1 = PACKED ? L.first[bid + 1] : bid + 1;
+    for (int i = i0; i < i1; ++i) {
+        if (i > i0) __syncthreads();  // every wave is done with the LDS planes of the previous chunk
+        const Chunk ch = L.chunks[i];
+        const int x0 = ch.x0, y0 = ch.y0, z0 = ch.z0, zc = ch.zc;
+        if (L.tile_bulk[i]) {
+            PlaneBits all;
 #pragma unroll
-        for (int i = 0; i < PLANE_WORDS; ++i) all.w[i] = ~(uint64_t)0;
-        march<T, L23, L4, MODE, true, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
-                                  sq, sm, red, all);
-    } else {
-        march<T, L23, L4, MODE, false, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0, zc,
-                                   sq, sm, red, L.tile_planes[bid]);
+            for (int w = 0; w < PLANE_WORDS; ++w) all.w[w] = ~(uint64_t)0;
+            march<T, L23, L4, MODE, true, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0,
+                                             zc, sq, sm, red, all);
+        } else {
+            march<T, L23, L4, MODE, false, W>(L, q_in, v_in, F_in, q_out, v_out, F_out, cv, cF, dt, hdt, x0, y0, z0,
+                                              zc, sq, sm, red, L.tile_planes[i]);
+        }
     }
     if (STEP) grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
 }
@@ -1059,8 +1066,13 @@ __global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_p
                                                     FireDev* st) {
     const int nblocks = (int)gridDim.x;
     int bid = (int)blockIdx.x;
-    // keep neighbouring tiles on one XCD: dispatch is round-robin over 8 XCDs
-    if ((nblocks & 7) == 0) bid = (bid & 7) * (nblocks >> 3) + (bid >> 3);
+    // keep neighbouring tiles on one XCD: dispatch is round-robin over 8
+    // XCDs, so XCD x runs the blocks x, x + 8, ...; they take the x-th
+    // contiguous share of the plan (the first nblocks % 8 shares one longer)
+    {
+        const int x = bid & 7, q = nblocks >> 3, r = nblocks & 7;
+        bid = x * q + (x < r ? x : r) + (bid >> 3);
+    }
     step_block<T, L23, L4, MODE, W>(L, b, qin, Fout, partials, st, nblocks, bid);
 }
 
@@ -1456,7 +1468,7 @@ __global__ __launch_bounds__(256) void k_directors(LatDev L, const T* __restrict
 // launchers
 static int hip_status(hipError_t e) { return e == hipSuccess ? LQ_OK : LQ_EHIP; }
 
-int64_t n_step_blocks(const LatDev& L) { return L.nchunks; }
+int64_t n_step_blocks(const LatDev& L) { return L.nblocks; }
 
 // Resident blocks per compute unit of the fused FIRE step kernel.
 template <typename T, bool L23, bool L4, int W>

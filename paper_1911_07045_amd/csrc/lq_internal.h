@@ -139,7 +139,8 @@ struct LatDev {
     int per[3];
     int64_t N;
     const uint8_t* mask;
-    const Chunk* chunks;       // per block of the step kernels
+    const Chunk* chunks;       // of the step kernels, in block order
+    const int32_t* first;      // block b of the step kernels marches chunks first[b] .. first[b + 1] - 1
     const uint8_t* tile_bulk;  // per chunk, 1: every site of the padded tile has mask M_FULL
     const PlaneBits* tile_planes;  // per chunk
     int n_anch;
@@ -148,7 +149,8 @@ struct LatDev {
     const void* anch_force;     // ANCH_FSTRIDE per anchored site, element type of the field
     double ext[5];              // constant external-field force per simulated site
     double A, B, C, L1, L2, L3, L4;
-    int nchunks;  // blocks of one step launch
+    int nchunks;  // chunks of one step launch
+    int nblocks;  // blocks of one step launch
     int wide;     // tile width kind of the step kernels (1 wide, 0 narrow)
 };
 

@@ -136,8 +136,8 @@ def lib():
             "lq_director_field": (C.c_int, [vp, vp, vp, vp, vp, C.c_double, C.POINTER(C.c_int64)]),
             "lq_stream_copy": (C.c_int, [C.POINTER(vp), C.POINTER(vp), i32, i64, i32, vp]),
             "lq_step_plan": (C.c_int, [C.POINTER(Params), C.POINTER(Object), i32, i64, C.POINTER(C.c_int32),
-                                       C.POINTER(C.c_uint8), i64, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
-                                       C.POINTER(C.c_int32)]),
+                                       C.POINTER(C.c_uint8), C.POINTER(C.c_int32), i64, C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "lq_last_error": (C.c_char_p, [vp]),
             "lq_batch_create": (C.c_int, [i32, vp, C.POINTER(vp)]),
             "lq_batch_destroy": (C.c_int, [vp]),
@@ -482,22 +482,25 @@ def step_plan(shape, periodic=(True, True, True), prec="f64", objects=(), reside
               C_=1.73, L1=2.32, L2=0.0, L3=0.0, L4=0.0):
     """lq_step_plan (host only): the step kernels' chunks for this lattice on a
     device with `resident` resident step blocks.  Returns (chunks, bulk,
-    (tile_x, tile_y)) with chunks an int32 array of rows (x0, y0, z0, zc) in
-    launch order and bulk a uint8 array."""
+    (tile_x, tile_y), block) with chunks an int32 array of rows (x0, y0, z0,
+    zc) in launch order, bulk a uint8 array and block the int32 index of the
+    block that marches each chunk."""
     import numpy as np
     p = make_params(shape, periodic, prec, A, B, C_, L1, L2, L3, L4)
     objs, no = make_objects(list(objects))
     n = C.c_int64()
     tx, ty = C.c_int32(), C.c_int32()
-    _check(lib().lq_step_plan(C.byref(p), objs, no, int(resident), None, None, 0, C.byref(n), C.byref(tx),
-                              C.byref(ty)))
+    _check(lib().lq_step_plan(C.byref(p), objs, no, int(resident), None, None, None, 0, C.byref(n),
+                              C.byref(tx), C.byref(ty)))
     chunks = np.zeros((n.value, 4), dtype=np.int32)
     bulk = np.zeros(n.value, dtype=np.uint8)
+    block = np.zeros(n.value, dtype=np.int32)
     _check(lib().lq_step_plan(C.byref(p), objs, no, int(resident),
                               chunks.ctypes.data_as(C.POINTER(C.c_int32)),
-                              bulk.ctypes.data_as(C.POINTER(C.c_uint8)), n.value, C.byref(n), C.byref(tx),
+                              bulk.ctypes.data_as(C.POINTER(C.c_uint8)),
+                              block.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n), C.byref(tx),
                               C.byref(ty)))
-    return chunks, bulk, (tx.value, ty.value)
+    return chunks, bulk, (tx.value, ty.value), block
 
 
 def stream_copy(src, dst, width=16, stream=None):

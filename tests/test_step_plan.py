@@ -2,11 +2,13 @@
 
 Every plan must cover each column tile's planes exactly once, keep chunks
 within 1 .. 256 planes (at least 4 where the lattice allows), flag as bulk
-exactly the chunks whose padded neighbourhood is all full bulk sites, fill
-one wave of resident blocks when the columns fit in one, cut one-constant
-lattices at the same planes in every column, balance the cost of L2/L3
-chunks, and give every XCD (each contiguous eighth of the launch order) its
-share of the wall chunks when the lattice takes many waves.
+exactly the chunks whose padded neighbourhood is all full bulk sites, give
+every block one or two chunks (listed together), stay within one wave of
+resident blocks when the columns fit in one, cut one-constant lattices at
+the same planes in every column, balance the cost of L2/L3 blocks (packing
+two chunks into a block where whole chunks per column cannot), and give
+every XCD (each contiguous eighth of the launch order) its share of the
+wall chunks when the lattice takes many waves.
 """
 import numpy as np
 import pytest
@@ -55,9 +57,12 @@ def padded_all_full(full, periodic, x0, y0, z0, zc, tx, ty):
 
 def check_plan(cfg, prec, resident):
     shape, periodic, objs = cfg["shape"], cfg["periodic"], cfg["objects"]
-    chunks, bulk, (tx, ty) = lqfire.step_plan(shape, periodic, prec, objs, resident, L1=cfg["L1"],
-                                              L2=cfg.get("L2", 0.0), L3=cfg.get("L3", 0.0))
+    chunks, bulk, (tx, ty), block = lqfire.step_plan(shape, periodic, prec, objs, resident, L1=cfg["L1"],
+                                                     L2=cfg.get("L2", 0.0), L3=cfg.get("L3", 0.0))
     nx, ny, nz = shape
+    # blocks are numbered 0, 1, ... in launch order, each with one or two chunks
+    assert block[0] == 0 and (np.diff(block) >= 0).all() and (np.diff(block) <= 1).all()
+    assert (np.bincount(block) <= 2).all()
     cols = {}
     for x0, y0, z0, zc in chunks:
         assert x0 % tx == 0 and y0 % ty == 0 and 0 <= x0 < nx and 0 <= y0 < ny
@@ -75,31 +80,50 @@ def check_plan(cfg, prec, resident):
     full = full_mask(shape, periodic, objs)
     for (x0, y0, z0, zc), b in zip(chunks, bulk):
         assert bool(b) == padded_all_full(full, periodic, x0, y0, z0, zc, tx, ty)
-    return chunks, bulk, cols, (tx, ty), full
+    return chunks, bulk, cols, (tx, ty), full, block
+
+
+def block_costs(chunks, bulk, block, full, periodic, tx, ty, g):
+    """The planner's cost model: per chunk its planes (1, or g for a plane
+    whose 3 x 3 x 3 neighbourhoods are not all full; the planner takes 3),
+    13% more unless the whole padded chunk is full, plus 2; per block
+    the sum of its chunks."""
+    costs = np.zeros(block.max() + 1)
+    for (x0, y0, z0, zc), b, k in zip(chunks, bulk, block):
+        c = sum(1.0 if padded_all_full(full, periodic, x0, y0, f, 1, tx, ty) else g for f in range(z0, z0 + zc))
+        costs[k] += c * (1.0 if b else 1.13) + 2.0
+    return costs
 
 
 def test_plan_l23_colloid_slab_fills_one_wave_and_balances_cost():
     cfg = synth.colloid_slab(64)
     cfg["objects"][2]["radius"] = 8.0
     resident = 64
-    chunks, bulk, cols, (tx, ty), full = check_plan(cfg, "f32", resident)
-    assert len(chunks) == resident
-    # cost: 1 per plane whose 3 x 3 x 3 neighbourhoods are all full, else 3
-    costs = []
-    for x0, y0, z0, zc in chunks:
-        c = 0.0
-        for f in range(z0, z0 + zc):
-            c += 1.0 if padded_all_full(full, cfg["periodic"], x0, y0, f, 1, tx, ty) else 3.0
-        costs.append(c)
-    costs = np.array(costs)
-    # a cut lands within one plane (cost <= 3) of its equal-cost point
-    assert costs.max() <= costs.sum() / len(costs) + 2 * 3.0 + 1.0
+    chunks, bulk, cols, (tx, ty), full, block = check_plan(cfg, "f32", resident)
+    assert len(chunks) == resident and (np.bincount(block) == 1).all()
+    costs = block_costs(chunks, bulk, block, full, cfg["periodic"], tx, ty, 3.0)
+    # a cut lands within one plane (cost <= 3.4) of its equal-cost point
+    assert costs.max() <= costs.sum() / resident + 2 * 3.4 + 1.0
     assert not bulk.all() and bulk.any()
+
+
+def test_plan_packs_chunks_where_whole_chunks_cannot_balance():
+    # 128^3 colloid slab in FP64: 64 columns for 256 resident blocks
+    cfg = synth.colloid_slab(128)
+    chunks, bulk, cols, (tx, ty), full, block = check_plan(cfg, "f64", 256)
+    n_blocks = block.max() + 1
+    assert n_blocks <= 256
+    assert (np.bincount(block) == 2).any()
+    costs = block_costs(chunks, bulk, block, full, cfg["periodic"], tx, ty, 3.0)
+    # whole chunks per column leave the costliest block above 1.25x the mean
+    # cost per resident block; packed, it stays within 1.12x
+    assert costs.max() <= 1.12 * costs.sum() / 256
 
 
 def test_plan_l1_cuts_every_column_alike():
     cfg = synth.multi_colloid(64, n_spheres=3, r_lo=4.0, r_hi=7.0)
-    chunks, bulk, cols, _, _ = check_plan(cfg, "f32", 32)
+    chunks, bulk, cols, _, _, block = check_plan(cfg, "f32", 32)
+    assert (np.bincount(block) == 1).all()
     cuts = {tuple(sorted(r)) for r in cols.values()}
     assert len(cuts) == 1
     assert len(chunks) <= 32
@@ -112,7 +136,8 @@ def test_plan_many_waves_share_walls_among_xcds():
             dict(kind="wall", axis=2, plane=nz - 1, law="rp", W=2.0, dir="normal")]
     cfg = dict(shape=(64, 64, nz), periodic=(True, True, True), objects=objs, L1=2.32, L2=1.16, L3=1.16)
     resident = 4  # far fewer resident blocks than columns: many waves of 128-plane chunks
-    chunks, bulk, cols, _, _ = check_plan(cfg, "f32", resident)
+    chunks, bulk, cols, _, _, block = check_plan(cfg, "f32", resident)
+    assert (np.bincount(block) == 1).all()
     assert all(zc == 128 for _, _, _, zc in chunks)
     assert len(chunks) == 8 * 4
     walls = np.array([(z0 == 0) or (z0 + zc == nz) for _, _, z0, zc in chunks])
@@ -130,7 +155,7 @@ def test_plan_small_and_ragged_boxes(shape, periodic, prec):
     c = [(s - 1) / 2.0 for s in shape]
     objs = [dict(kind="sphere", center=tuple(c), radius=min(shape) / 4.0, law="rp", W=2.0, dir="normal")]
     cfg = dict(shape=shape, periodic=periodic, objects=objs, L1=2.32, L2=0.7, L3=0.3)
-    chunks, bulk, cols, _, _ = check_plan(cfg, prec, 512)
+    chunks, bulk, cols, _, _, _ = check_plan(cfg, prec, 512)
     cfg["L2"] = cfg["L3"] = 0.0
     check_plan(cfg, prec, 512)
 
