@@ -678,8 +678,13 @@ __device__ void grid_finish(double r[4], double* partials, FireDev* st, int nblo
     __syncthreads();
     block_reduce4(s, scratch);
     if (threadIdx.x == 0) {
-        fire_control(st, s[0], s[1], s[2], s[3]);
-        st->ticket = 0;
+        // the controller on a register copy of the state: one round trip to
+        // read it and one to write it, instead of a chain of dependent
+        // global reads (no other block touches the state any more)
+        FireDev c = *st;
+        fire_control(&c, s[0], s[1], s[2], s[3]);
+        c.ticket = 0;
+        *st = c;
         __threadfence();
     }
 }
