@@ -725,11 +725,17 @@ static int64_t partial_slots(const lq_lattice* lat) {
 
 static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
+// Workspace: the second buffer of q, v and F; two slots of block partials
+// (step k writes slot k & 1 while step k + 1 reads it); the controller
+// state st[2] and its DcCtl word.
+static int64_t partials_bytes(const lq_lattice* lat) {
+    return align256(2 * partial_slots(lat) * 4 * (int64_t)sizeof(double));
+}
+
 int64_t lq_workspace_bytes(const lq_lattice* lat) {
     if (!lat) return -1;
     const int64_t field = align256(5 * lat->N * (int64_t)elem_size(lat));
-    return 3 * field + align256(partial_slots(lat) * 4 * (int64_t)sizeof(double)) +
-           align256((int64_t)sizeof(FireDev));
+    return 3 * field + partials_bytes(lat) + align256(2 * (int64_t)sizeof(FireDev) + (int64_t)sizeof(DcCtl));
 }
 
 static int check_fire_params(lq_lattice* lat, const lq_fire_params* fp) {
@@ -762,7 +768,7 @@ static int bind_buffers(lq_lattice* lat, void* q, void* v, void* F, void* worksp
     void* v1 = ws + field;
     void* F1 = ws + 2 * field;
     lat->d_partials = (double*)(ws + 3 * field);
-    lat->d_state = (FireDev*)(ws + 3 * field + align256(partial_slots(lat) * 4 * (int64_t)sizeof(double)));
+    lat->d_state = (FireDev*)(ws + 3 * field + partials_bytes(lat));
     lat->q = q;
     lat->v = v;
     lat->F = F;

@@ -1006,13 +1006,59 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
     red[3] = fmax(red[3], (double)fmax_abs);
 }
 
+// Sums the partials of nblocks blocks in block order (every block of a
+// kernel that calls this gets the same sums: they depend on the block size
+// and nblocks only).
+__device__ __forceinline__ void sum_partials(const double* partials, int nblocks, double s[4],
+                                             double (*scratch)[4]) {
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        const double* p = partials + 4 * (int64_t)b;
+        s[0] += p[0]; s[1] += p[1]; s[2] += p[2]; s[3] = fmax(s[3], p[3]);
+    }
+    __syncthreads();
+    block_reduce4(s, scratch);
+}
+
+// Start of step kernel k (1-based within a call) of a lattice: the
+// controller on the reduction of step k - 1, in every block (the same sums
+// in the same order give every block the same result), so that no block
+// waits for a last one to finish the previous kernel.  Block 0 keeps the
+// new state in st[(k - 1) & 1].  Returns true (every thread) when the run has
+// stopped; the step's parameters go to cd (dt, c_v, c_F, mu) and ci (cur).
+__device__ bool dc_begin(FireDev* st, const double* partials, int nblocks, int k, int bid,
+                         double (*scratch)[4], double* cd, int* ci) {
+    DcCtl* ctl = (DcCtl*)(st + 2);
+    if (*(volatile const int32_t*)&ctl->halt) return true;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (k >= 2) sum_partials(partials + 4 * (int64_t)((k - 1) & 1) * nblocks, nblocks, s, scratch);
+    if (threadIdx.x == 0) {
+        FireDev c = st[k >= 2 ? (k & 1) : 0];
+        if (k >= 2 && !c.done) fire_control(&c, s[0], s[1], s[2], s[3]);
+        const int stop = c.done ? 1 : 0;
+        if (bid == 0) {
+            if (k >= 2) st[(k - 1) & 1] = c;
+            if (stop) {
+                ctl->slot = k >= 2 ? ((k - 1) & 1) : 0;
+                ctl->halt = 1;
+            }
+        }
+        cd[0] = c.dt; cd[1] = c.c_v; cd[2] = c.c_F; cd[3] = c.mu;
+        ci[0] = c.cur; ci[1] = stop;
+    }
+    __syncthreads();
+    return ci[1] != 0;
+}
+
 // One block of the force / FIRE step: tile `bid` of lattice L.  `nblocks`
 // is the lattice's own tile count; partials are indexed by tile, so the
-// reduction order does not depend on how blocks are dispatched.
-template <typename T, bool L23, bool L4, int MODE, int W>
+// reduction order does not depend on how blocks are dispatched.  DC (the
+// step kernels of a lattice): the controller runs at the start of the next
+// step kernel (dc_begin) and the partials of step k go to slot k & 1; else
+// (the batched kernels) the last block of each step runs it (grid_finish).
+template <typename T, bool L23, bool L4, int MODE, int W, bool DC>
 __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, const T* __restrict__ qin,
                                            T* __restrict__ Fout, double* partials, FireDev* st,
-                                           int nblocks, int bid) {
+                                           int nblocks, int bid, int k) {
     constexpr int NS = 4;
     using G = Tile<T, L23, W>;
     constexpr int PX = G::PX, PY = G::PY;
@@ -1020,21 +1066,29 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
     __shared__ uint8_t sm[NS][PY][PX];
     __shared__ double scratch[G::N / 64][4];
     __shared__ int last_flag;
+    __shared__ double ctl_d[4];
+    __shared__ int ctl_i[2];
 
     constexpr bool STEP = MODE != MODE_FORCE;
     const T *q_in, *v_in = nullptr, *F_in = nullptr;
     T *q_out = nullptr, *v_out = nullptr, *F_out;
     T cv = T(1), cF = T(0), dt = T(0), hdt = T(0);
     if (STEP) {
-        if (st->done) return;
-        const int cur = st->cur;
+        int cur;
+        double dtd, c_v, c_F, mu;
+        if (DC) {
+            if (dc_begin(st, partials, nblocks, k, bid, scratch, ctl_d, ctl_i)) return;
+            cur = ctl_i[0]; dtd = ctl_d[0]; c_v = ctl_d[1]; c_F = ctl_d[2]; mu = ctl_d[3];
+        } else {
+            if (st->done) return;
+            cur = st->cur; dtd = st->dt; c_v = st->c_v; c_F = st->c_F; mu = st->mu;
+        }
         // selects rather than indexing by cur, which would put b in scratch
         q_in = cur ? b.q[1] : b.q[0]; v_in = cur ? b.v[1] : b.v[0]; F_in = cur ? b.F[1] : b.F[0];
         q_out = cur ? b.q[0] : b.q[1]; v_out = cur ? b.v[0] : b.v[1]; F_out = cur ? b.F[0] : b.F[1];
-        const double dtd = st->dt;
         dt = T(dtd); hdt = T(0.5 * dtd);
-        if (MODE == MODE_FIRE) { cv = T(st->c_v); cF = T(st->c_F); }
-        if (MODE == MODE_NAG) cv = T(st->mu);
+        if (MODE == MODE_FIRE) { cv = T(c_v); cF = T(c_F); }
+        if (MODE == MODE_NAG) cv = T(mu);
     } else {
         q_in = qin;
         F_out = Fout;
@@ -1060,7 +1114,40 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
                                               zc, sq, sm, red, L.tile_planes[i]);
         }
     }
-    if (STEP) grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
+    if (STEP && DC) {
+        block_reduce4(red, scratch);
+        if (threadIdx.x == 0) {
+            double* p = partials + 4 * ((int64_t)(k & 1) * nblocks + bid);
+            p[0] = red[0]; p[1] = red[1]; p[2] = red[2]; p[3] = red[3];
+        }
+    } else if (STEP) {
+        grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
+    }
+}
+
+// After the k_steps step kernels of a call: the controller on the last
+// step's reduction (the same sums, in the same order, as in a step kernel
+// of NT threads), or the state the run stopped with, into st[0].
+template <int NT>
+__global__ __launch_bounds__(NT) void k_dc_control(FireDev* st, const double* partials, int nblocks, int k_steps) {
+    __shared__ double scratch[NT / 64][4];
+    DcCtl* ctl = (DcCtl*)(st + 2);
+    if (ctl->halt) {
+        if (threadIdx.x == 0) {
+            const int sl = ctl->slot;
+            if (sl != 0) st[0] = st[sl];
+            ctl->halt = 0;
+        }
+        return;
+    }
+    if (k_steps <= 0) return;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    sum_partials(partials + 4 * (int64_t)(k_steps & 1) * nblocks, nblocks, s, scratch);
+    if (threadIdx.x == 0) {
+        FireDev c = st[k_steps >= 2 ? ((k_steps - 1) & 1) : 0];
+        fire_control(&c, s[0], s[1], s[2], s[3]);
+        st[0] = c;
+    }
 }
 
 // L4: the kernel evaluates the chiral term (a kernel of its own, so that the
@@ -1068,7 +1155,7 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
 template <typename T, bool L23, bool L4, int MODE, int W>
 __global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_per_eu(L4 ? 1 : Tile<T, L23, W>::WAVES))) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
                                                     T* __restrict__ Fout, double* partials,
-                                                    FireDev* st) {
+                                                    FireDev* st, int k) {
     const int nblocks = (int)gridDim.x;
     int bid = (int)blockIdx.x;
     // keep neighbouring tiles on one XCD: dispatch is round-robin over 8
@@ -1078,7 +1165,7 @@ __global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_p
         const int x = bid & 7, q = nblocks >> 3, r = nblocks & 7;
         bid = x * q + (x < r ? x : r) + (bid >> 3);
     }
-    step_block<T, L23, L4, MODE, W>(L, b, qin, Fout, partials, st, nblocks, bid);
+    step_block<T, L23, L4, MODE, W, true>(L, b, qin, Fout, partials, st, nblocks, bid, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -1106,8 +1193,8 @@ __global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_p
         b.q[i] = (T*)M.q[i]; b.v[i] = (T*)M.v[i]; b.F[i] = (T*)M.F[i];
     }
     const LatDev& L = M.L;
-    step_block<T, L23, L23, MODE_FIRE, W>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
-                             (int)blockIdx.x - off[m]);
+    step_block<T, L23, L23, MODE_FIRE, W, false>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
+                                                 (int)blockIdx.x - off[m], 0);
 }
 
 __global__ void k_batch_begin(const MemberDev* __restrict__ mem, int n_members, int64_t n_steps) {
@@ -1178,6 +1265,7 @@ __global__ __launch_bounds__(256) void k_init_reduce(const T* __restrict__ F, co
 
 __global__ void k_begin(FireDev* st, int64_t n_steps) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ((DcCtl*)(st + 2))->halt = 0;
         if (st->status == LQ_RUNNING) {
             st->done = 0;
             st->stop_at = st->step + n_steps;
@@ -1505,50 +1593,61 @@ static int grid_1d(int64_t n) {
 
 template <typename T, int MODE, int W>
 static void launch_march(const LatDev& L, bool l23, const Bufs<T>& b, const void* q, void* F, double* partials,
-                         FireDev* st, hipStream_t s) {
+                         FireDev* st, int k, hipStream_t s) {
     const dim3 g((unsigned)n_step_blocks(L));
     if (l23 && L.L4 != 0.0)
-        k_march<T, true, true, MODE, W><<<g, Tile<T, true, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st);
+        k_march<T, true, true, MODE, W><<<g, Tile<T, true, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st, k);
     else if (l23)
-        k_march<T, true, false, MODE, W><<<g, Tile<T, true, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st);
+        k_march<T, true, false, MODE, W><<<g, Tile<T, true, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st, k);
     else
-        k_march<T, false, false, MODE, W><<<g, Tile<T, false, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st);
+        k_march<T, false, false, MODE, W><<<g, Tile<T, false, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st, k);
 }
 
 template <typename T, int MODE>
 static void launch_march_any(const LatDev& L, bool l23, const Bufs<T>& b, const void* q, void* F, double* partials,
-                             FireDev* st, hipStream_t s) {
-    if (L.wide) launch_march<T, MODE, 1>(L, l23, b, q, F, partials, st, s);
-    else launch_march<T, MODE, 0>(L, l23, b, q, F, partials, st, s);
+                             FireDev* st, int k, hipStream_t s) {
+    if (L.wide) launch_march<T, MODE, 1>(L, l23, b, q, F, partials, st, k, s);
+    else launch_march<T, MODE, 0>(L, l23, b, q, F, partials, st, k, s);
 }
 
 int launch_forces(const LatDev& L, bool l23, int prec, const void* q, void* F, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    if (prec == LQ_F64) launch_march_any<double, MODE_FORCE>(L, l23, Bufs<double>{}, q, F, nullptr, nullptr, s);
-    else launch_march_any<float, MODE_FORCE>(L, l23, Bufs<float>{}, q, F, nullptr, nullptr, s);
+    if (prec == LQ_F64) launch_march_any<double, MODE_FORCE>(L, l23, Bufs<double>{}, q, F, nullptr, nullptr, 0, s);
+    else launch_march_any<float, MODE_FORCE>(L, l23, Bufs<float>{}, q, F, nullptr, nullptr, 0, s);
     return hip_status(hipGetLastError());
 }
 
 template <int MODE>
 static void launch_step(const LatDev& L, bool l23, int prec, const void* bufs, double* partials, FireDev* st,
-                        hipStream_t s) {
+                        int k, hipStream_t s) {
     if (prec == LQ_F64)
-        launch_march_any<double, MODE>(L, l23, *(const Bufs<double>*)bufs, nullptr, nullptr, partials, st, s);
+        launch_march_any<double, MODE>(L, l23, *(const Bufs<double>*)bufs, nullptr, nullptr, partials, st, k, s);
     else
-        launch_march_any<float, MODE>(L, l23, *(const Bufs<float>*)bufs, nullptr, nullptr, partials, st, s);
+        launch_march_any<float, MODE>(L, l23, *(const Bufs<float>*)bufs, nullptr, nullptr, partials, st, k, s);
 }
+
+// Index of step kernel i (1-based) of a call as the step kernels use it:
+// only whether it is the first, and its parity, matter (kept within int).
+static int step_index(int64_t i) { return i <= 1 ? (int)i : 2 + (int)(i & 1); }
 
 int launch_fire_steps(const LatDev& L, bool l23, int prec, int method, const void* bufs, double* partials,
                       FireDev* st, int64_t n_steps, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    for (int64_t i = 0; i < n_steps; ++i) {
-        if (method == LQ_METHOD_GD) launch_step<MODE_GD>(L, l23, prec, bufs, partials, st, s);
-        else if (method == LQ_METHOD_NESTEROV) launch_step<MODE_NAG>(L, l23, prec, bufs, partials, st, s);
-        else launch_step<MODE_FIRE>(L, l23, prec, bufs, partials, st, s);
+    for (int64_t i = 1; i <= n_steps; ++i) {
+        const int k = step_index(i);
+        if (method == LQ_METHOD_GD) launch_step<MODE_GD>(L, l23, prec, bufs, partials, st, k, s);
+        else if (method == LQ_METHOD_NESTEROV) launch_step<MODE_NAG>(L, l23, prec, bufs, partials, st, k, s);
+        else launch_step<MODE_FIRE>(L, l23, prec, bufs, partials, st, k, s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return LQ_EHIP;
     }
-    return LQ_OK;
+    // the controller on the last step's reduction, with the step kernel's block size
+    const int nt = tile_threads(prec, l23, L.wide), nb = (int)n_step_blocks(L), kl = step_index(n_steps);
+    if (nt == 1024) k_dc_control<1024><<<1, 1024, 0, s>>>(st, partials, nb, kl);
+    else if (nt == 512) k_dc_control<512><<<1, 512, 0, s>>>(st, partials, nb, kl);
+    else if (nt == 256) k_dc_control<256><<<1, 256, 0, s>>>(st, partials, nb, kl);
+    else return LQ_EINVAL;
+    return hip_status(hipGetLastError());
 }
 
 int launch_fire_init_reduce(const LatDev& L, int prec, const void* F, const void* v,

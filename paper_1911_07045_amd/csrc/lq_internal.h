@@ -171,6 +171,16 @@ struct FireDev {
     double mu;        // Nesterov momentum
 };
 
+// The state of a lattice's step kernels: FireDev st[2] followed by DcCtl.
+// st[0] holds the controller state between calls.  Within a call, step
+// kernel k (1-based) first runs the controller on the reduction of step
+// k - 1 (every block, identically) and block 0 stores the result in
+// st[(k - 1) & 1]; a block that finds the run stopped sets halt.
+struct DcCtl {
+    int32_t halt;  // a step kernel of this call found the run stopped
+    int32_t slot;  // ... and left the final state in st[slot]
+};
+
 // march kernel variants
 enum : int { MODE_FORCE = 0, MODE_FIRE = 1, MODE_GD = 2, MODE_NAG = 3 };
 
