@@ -1024,11 +1024,16 @@ __device__ __forceinline__ void sum_partials(const double* partials, int nblocks
 // in the same order give every block the same result), so that no block
 // waits for a last one to finish the previous kernel.  Block 0 keeps the
 // new state in st[(k - 1) & 1].  Returns true (every thread) when the run has
-// stopped; the step's parameters go to cd (dt, c_v, c_F, mu) and ci (cur).
+// stopped; the step's parameters go to cd (dt, c_v, c_F, mu) and ci (cur,
+// stop; ci[2] takes the stop word).
 __device__ bool dc_begin(FireDev* st, const double* partials, int nblocks, int k, int bid,
                          double (*scratch)[4], double* cd, int* ci) {
     DcCtl* ctl = (DcCtl*)(st + 2);
-    if (*(volatile const int32_t*)&ctl->halt) return true;
+    // one read of the stop word per block: waves that read it apart could see
+    // different values while block 0 of this kernel sets it
+    if (threadIdx.x == 0) ci[2] = ((volatile const DcCtl*)ctl)->halt;
+    __syncthreads();
+    if (ci[2]) return true;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     if (k >= 2) sum_partials(partials + 4 * (int64_t)((k - 1) & 1) * nblocks, nblocks, s, scratch);
     if (threadIdx.x == 0) {
@@ -1067,7 +1072,7 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
     __shared__ double scratch[G::N / 64][4];
     __shared__ int last_flag;
     __shared__ double ctl_d[4];
-    __shared__ int ctl_i[2];
+    __shared__ int ctl_i[3];
 
     constexpr bool STEP = MODE != MODE_FORCE;
     const T *q_in, *v_in = nullptr, *F_in = nullptr;
