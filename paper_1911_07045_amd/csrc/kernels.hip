@@ -1057,9 +1057,9 @@ __device__ bool dc_begin(FireDev* st, const double* partials, int nblocks, int k
 // One block of the force / FIRE step: tile `bid` of lattice L.  `nblocks`
 // is the lattice's own tile count; partials are indexed by tile, so the
 // reduction order does not depend on how blocks are dispatched.  DC (the
-// step kernels of a lattice): the controller runs at the start of the next
-// step kernel (dc_begin) and the partials of step k go to slot k & 1; else
-// (the batched kernels) the last block of each step runs it (grid_finish).
+// step kernels): the controller runs at the start of the next step kernel
+// (dc_begin) and the partials of step k go to slot k & 1; else (the FIRE
+// initialisation's reduction) the last block runs it (grid_finish).
 template <typename T, bool L23, bool L4, int MODE, int W, bool DC>
 __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, const T* __restrict__ qin,
                                            T* __restrict__ Fout, double* partials, FireDev* st,
@@ -1134,8 +1134,7 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
 // step's reduction (the same sums, in the same order, as in a step kernel
 // of NT threads), or the state the run stopped with, into st[0].
 template <int NT>
-__global__ __launch_bounds__(NT) void k_dc_control(FireDev* st, const double* partials, int nblocks, int k_steps) {
-    __shared__ double scratch[NT / 64][4];
+__device__ void dc_final(FireDev* st, const double* partials, int nblocks, int k_steps, double (*scratch)[4]) {
     DcCtl* ctl = (DcCtl*)(st + 2);
     if (ctl->halt) {
         if (threadIdx.x == 0) {
@@ -1153,6 +1152,20 @@ __global__ __launch_bounds__(NT) void k_dc_control(FireDev* st, const double* pa
         fire_control(&c, s[0], s[1], s[2], s[3]);
         st[0] = c;
     }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_dc_control(FireDev* st, const double* partials, int nblocks, int k_steps) {
+    __shared__ double scratch[NT / 64][4];
+    dc_final<NT>(st, partials, nblocks, k_steps, scratch);
+}
+
+// The same for every member of a batch group (one block per member).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch_dc_control(const MemberDev* __restrict__ mem, int k_steps) {
+    __shared__ double scratch[NT / 64][4];
+    const MemberDev& M = mem[blockIdx.x];
+    dc_final<NT>(M.st, M.partials, M.nblocks, k_steps, scratch);
 }
 
 // L4: the kernel evaluates the chiral term (a kernel of its own, so that the
@@ -1189,7 +1202,7 @@ __device__ __forceinline__ int member_of(const int* __restrict__ off, int n, int
 
 template <typename T, bool L23, int W>
 __global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_per_eu(Tile<T, L23, W>::WAVES))) void k_march_batch(const MemberDev* __restrict__ mem,
-                                                          const int* __restrict__ off, int n_members) {
+                                                          const int* __restrict__ off, int n_members, int k) {
     const int m = member_of(off, n_members, (int)blockIdx.x);
     const MemberDev& M = mem[m];
     Bufs<T> b;
@@ -1198,14 +1211,15 @@ __global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_p
         b.q[i] = (T*)M.q[i]; b.v[i] = (T*)M.v[i]; b.F[i] = (T*)M.F[i];
     }
     const LatDev& L = M.L;
-    step_block<T, L23, L23, MODE_FIRE, W, false>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
-                                                 (int)blockIdx.x - off[m], 0);
+    step_block<T, L23, L23, MODE_FIRE, W, true>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
+                                                (int)blockIdx.x - off[m], k);
 }
 
 __global__ void k_batch_begin(const MemberDev* __restrict__ mem, int n_members, int64_t n_steps) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n_members) return;
     FireDev* st = mem[m].st;
+    ((DcCtl*)(st + 2))->halt = 0;
     if (st->status == LQ_RUNNING) {
         st->done = 0;
         st->stop_at = st->step + n_steps;
@@ -1728,10 +1742,21 @@ int launch_uniaxial(const LatDev& L, int prec, const double* dirs, double S, voi
 }
 
 template <typename T, int W>
-static void launch_batch_group(bool l23, const MemberDev* mem, const int* off, int n, int tiles, hipStream_t s) {
+static void launch_batch_group(bool l23, const MemberDev* mem, const int* off, int n, int tiles, int k,
+                               hipStream_t s) {
     if (n <= 0) return;
-    if (l23) k_march_batch<T, true, W><<<tiles, Tile<T, true, W>::N, 0, s>>>(mem, off, n);
-    else k_march_batch<T, false, W><<<tiles, Tile<T, false, W>::N, 0, s>>>(mem, off, n);
+    if (l23) k_march_batch<T, true, W><<<tiles, Tile<T, true, W>::N, 0, s>>>(mem, off, n, k);
+    else k_march_batch<T, false, W><<<tiles, Tile<T, false, W>::N, 0, s>>>(mem, off, n, k);
+}
+
+// The final controller of every member of a group, with the group's block size.
+template <typename T, int W>
+static void launch_batch_control(bool l23, const MemberDev* mem, int n, int k, hipStream_t s) {
+    if (n <= 0) return;
+    const int nt = l23 ? Tile<T, true, W>::N : Tile<T, false, W>::N;
+    if (nt == 1024) k_batch_dc_control<1024><<<n, 1024, 0, s>>>(mem, k);
+    else if (nt == 512) k_batch_dc_control<512><<<n, 512, 0, s>>>(mem, k);
+    else k_batch_dc_control<256><<<n, 256, 0, s>>>(mem, k);
 }
 
 int launch_batch_steps(int prec, bool l23, const MemberDev* mem, int n_narrow, const int* tile_off,
@@ -1742,16 +1767,26 @@ int launch_batch_steps(int prec, bool l23, const MemberDev* mem, int n_narrow, c
     const int nb = (n_members + 63) / 64;
     k_batch_begin<<<nb, 64, 0, s>>>(mem, n_members, n_steps);
     if (hipGetLastError() != hipSuccess) return LQ_EHIP;
-    for (int64_t i = 0; i < n_steps; ++i) {
+    for (int64_t i = 1; i <= n_steps; ++i) {
+        const int k = step_index(i);
         if (prec == LQ_F64) {
-            launch_batch_group<double, 0>(l23, mem, tile_off, n_narrow, tiles_narrow, s);
-            launch_batch_group<double, 1>(l23, mem + n_narrow, tile_off_wide, n_wide, tiles_wide, s);
+            launch_batch_group<double, 0>(l23, mem, tile_off, n_narrow, tiles_narrow, k, s);
+            launch_batch_group<double, 1>(l23, mem + n_narrow, tile_off_wide, n_wide, tiles_wide, k, s);
         } else {
-            launch_batch_group<float, 0>(l23, mem, tile_off, n_narrow, tiles_narrow, s);
-            launch_batch_group<float, 1>(l23, mem + n_narrow, tile_off_wide, n_wide, tiles_wide, s);
+            launch_batch_group<float, 0>(l23, mem, tile_off, n_narrow, tiles_narrow, k, s);
+            launch_batch_group<float, 1>(l23, mem + n_narrow, tile_off_wide, n_wide, tiles_wide, k, s);
         }
         if (hipGetLastError() != hipSuccess) return LQ_EHIP;
     }
+    const int kl = step_index(n_steps);
+    if (prec == LQ_F64) {
+        launch_batch_control<double, 0>(l23, mem, n_narrow, kl, s);
+        launch_batch_control<double, 1>(l23, mem + n_narrow, n_wide, kl, s);
+    } else {
+        launch_batch_control<float, 0>(l23, mem, n_narrow, kl, s);
+        launch_batch_control<float, 1>(l23, mem + n_narrow, n_wide, kl, s);
+    }
+    if (hipGetLastError() != hipSuccess) return LQ_EHIP;
     if (prec == LQ_F64) k_batch_finalize<double><<<total_fin, 256, 0, s>>>(mem, fin_off, n_members);
     else k_batch_finalize<float><<<total_fin, 256, 0, s>>>(mem, fin_off, n_members);
     if (hipGetLastError() != hipSuccess) return LQ_EHIP;
