@@ -461,6 +461,52 @@ def test_fire_steps_resume_bitwise():
             assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("stop", ["tolerance", "max_steps"])
+def test_stop_inside_a_call_equals_single_steps(stop):
+    """A run that stops inside one fire_step call (tolerance reached, or the
+    step limit) stops at the same step, with the same state and controller,
+    as the same run taken one step per call; later calls change nothing.
+    The step kernels run the controller of step k at the start of step
+    kernel k + 1, so this covers the stop found there and the kernels of the
+    call that follow it."""
+    say(f"[fire] stop inside a call: {stop}")
+    cfg = synth.colloid_slab(16, seed=8)
+    cfg["objects"][2]["radius"] = 3.0
+
+    def start(tol, cap):
+        lat = lqfire.lattice_from_config(cfg)
+        q = lat.set_uniaxial(to_dev(synth.random_directors(8, lat.N), torch.float64), lat.empty())
+        v, F = lat.empty(), lat.empty()
+        lat.fire_init(lqfire.make_fire_params(force_tol=tol, max_steps=cap), q, v, F)
+        return lat, q, v, F
+
+    if stop == "tolerance":
+        # the tolerance is the max|F| this run has after 300 steps: reached by then
+        lat, *_ = start(0.0, 10 ** 6)
+        tol, cap = lat.fire_step(300).maxF * (1.0 + 1e-12), 10 ** 6
+    else:
+        tol, cap = 0.0, 37
+    out = []
+    for mode in ("one call", "single steps"):
+        lat, q, v, F = start(tol, cap)
+        if mode == "one call":
+            rep = lat.fire_step(5000)
+        else:
+            rep = lat.fire_step(1)
+            while rep.status == lqfire.RUNNING and rep.step < 5000:
+                rep = lat.fire_step(1)
+        after = lat.fire_step(25)
+        assert after.as_dict() == rep.as_dict()
+        out.append((rep.as_dict(), q.cpu(), v.cpu(), F.cpu()))
+    (ra, *sa), (rb, *sb) = out
+    assert ra == rb
+    assert ra["status"] == (lqfire.CONVERGED if stop == "tolerance" else lqfire.MAX_STEPS)
+    assert 0 < ra["step"] < 5000 and (stop == "tolerance" or ra["step"] == cap)
+    for x, y in zip(sa, sb):
+        assert torch.equal(x, y)
+    say(f"  stopped at step {ra['step']}")
+
+
 @pytest.mark.parametrize("anchor_dir", [(1.0, 0.0, 0.0), "normal"])
 def test_minimize_reaches_exact_wall_minimum(ora, anchor_dir):
     """Walls preferring one director: the minimum is Q0 everywhere and
