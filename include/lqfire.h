@@ -217,7 +217,9 @@ typedef struct {
 } lq_fire_report;
 
 /* Bytes of device workspace lq_fire_init needs: a second q, v, F for the
- * ping-pong update, per-block partial sums and the device FIRE state. */
+ * ping-pong update, two slots of per-block partial sums (step k writes one
+ * while step k + 1 reads the other) and the device FIRE state (two copies and
+ * a stop word: each step kernel runs the controller of the step before it). */
 int64_t lq_workspace_bytes(const lq_lattice* lat);
 
 /* Binds q, v, F and the workspace to the lattice and starts FIRE: F = F(q),
