@@ -226,12 +226,12 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
     for (int64_t c = 0; c < ncol; ++c)
         for (int64_t i = 0; i < P; ++i)
             nonfull[(size_t)(c * (P + 1) + i + 1)] = nonfull[(size_t)(c * (P + 1) + i)] + (F(c, i) ? 0 : 1);
-    // one wave: chunks up to CHUNK_MAX planes; many waves: 128 planes (on the
-    // 512^3 patterned wall 3.84 ms per step, against 3.95 with 64 and 3.86
-    // with 256)
+    // one wave: chunks up to CHUNK_MAX planes; many waves: up to 96 planes,
+    // cut at equal-cost points (on the 512^3 patterned wall 3.752 ms per step,
+    // against 3.785 with 128 and 3.758 with 80 on one GPU)
     const int64_t zmin = 4;
     const bool one_wave = ncol * ((nz + CHUNK_MAX - 1) / CHUNK_MAX) <= resident;
-    const int64_t zmax = one_wave ? CHUNK_MAX : 128;
+    const int64_t zmax = one_wave ? CHUNK_MAX : 96;
     const int64_t m_lo = (nz + zmax - 1) / zmax;
     const int64_t m_hi = std::max<int64_t>(m_lo, nz / zmin);
     std::vector<int64_t> m((size_t)ncol, m_lo);
