@@ -145,11 +145,24 @@ static int check_dev_ptr(lq_lattice* lat, const void* ptr, const char* name) {
 }
 
 // Resident blocks of the fused step kernel on the whole device.
-static int64_t resident_blocks(const lq_params& p, int device, bool l23, int wide) {
+static int64_t resident_blocks(const lq_params& p, int device, bool l23, int wide, bool two = false) {
     int n_cu = 0;
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n_cu <= 0)
         n_cu = 256;
-    return (int64_t)n_cu * step_blocks_per_cu(p.prec, l23, p.L4 != 0.0, wide);
+    return (int64_t)n_cu * step_blocks_per_cu(p.prec, l23, p.L4 != 0.0, wide, two);
+}
+
+// The FP64 L2/L3 step kernel holds one wave per SIMD (its registers); held
+// to two (a few spilled), it hides more latency but spills.  Measured on one
+// GPU: the 128^3 colloid slab 0.153 -> 0.149 ms and the 128^3 bulk box
+// 0.131 -> 0.124 ms, but the 256^3 bulk box 0.875 -> 0.902 ms.  So the two-wave
+// kernel serves lattices whose one-wave chunks (at one block per compute
+// unit) would be shorter than 64 planes.
+static bool two_waves_for(const lq_params& p, int device, bool l23, int wide) {
+    if (p.prec != LQ_F64 || !l23 || p.L4 != 0.0 || !wide) return false;
+    const int64_t TX = tile_x(p.prec, l23, wide), TY = tile_y(p.prec, l23, wide);
+    const int64_t ncol = ((p.n[0] + TX - 1) / TX) * ((p.n[1] + TY - 1) / TY);
+    return ncol * p.n[2] < 64 * resident_blocks(p, device, l23, wide);
 }
 
 // Work of the step kernels.  A block marches one chunk: a run of planes of
@@ -436,7 +449,9 @@ static int upload_geometry(lq_lattice* lat, const Geometry& g) {
     d.A = p.A; d.B = p.B; d.C = p.C; d.L1 = p.L1; d.L2 = p.L2; d.L3 = p.L3; d.L4 = p.L4;
     d.wide = tile_wide_for(p.n[0], p.prec, lat->l23);
     ChunkPlan plan;
-    plan_chunks(p, lat->l23, d.wide, g.mask, resident_blocks(p, lat->device, lat->l23, d.wide), plan);
+    d.two_waves = two_waves_for(p, lat->device, lat->l23, d.wide) ? 1 : 0;
+    plan_chunks(p, lat->l23, d.wide, g.mask, resident_blocks(p, lat->device, lat->l23, d.wide, d.two_waves != 0),
+                plan);
     d.nchunks = (int)plan.chunks.size();
     d.nblocks = (int)plan.first.size() - 1;
     HIPCHK(lat, hipMalloc(&lat->d_first, plan.first.size() * sizeof(int32_t)));

@@ -359,7 +359,8 @@ __device__ __forceinline__ void anch_load(const LatDev& L, int arow1, AnchRow<T>
 // carries the anchoring bit, the site's anchoring form is AR (wide tiles,
 // loaded ahead by the caller) or row arow1 - 1 of the FP64 forms, read here
 // (narrow tiles: on the serving stream of small boxes this measured a lower
-// tail latency than the early loads).
+// tail latency than the early loads; FP64 L2/L3: the 40 registers of an early
+// row are what keeps that kernel from two waves per SIMD).
 template <typename T, bool L23, bool L4, bool BULK, int W>
 __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, uint32_t m0,
                                            const LatDev& L, const AnchRow<T>& AR, int arow1, T F[5]) {
@@ -529,7 +530,7 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
         }
     }
     // d/dq of 1/2 q^T K q + b^T q = K q + b, K from its upper triangle
-    if (!BULK && W == 1 && (m0 & M_ANCH)) {
+    if (!BULK && W == 1 && !(L23 && sizeof(T) == 8) && (m0 & M_ANCH)) {
         T Kq[5];
 #pragma unroll
         for (int a = 0; a < 5; ++a) Kq[a] = AR.b[a];
@@ -545,7 +546,7 @@ __device__ __forceinline__ void site_force(const Stencil<T, L23, BULK, W>& P, ui
 #pragma unroll
         for (int c = 0; c < 5; ++c) g[c] += Kq[c];
     }
-    if (!BULK && W == 0 && (m0 & M_ANCH)) {
+    if (!BULK && (W == 0 || (L23 && sizeof(T) == 8)) && (m0 & M_ANCH)) {
         // narrow tiles: the row of the FP64 form, read here
         const int at = arow1 - 1;
         if (at >= 0) {
@@ -894,9 +895,9 @@ __device__ __forceinline__ void march(const LatDev& L, const T* __restrict__ q_i
         // plane j is drifted and the block meets at the barrier.  Narrow tiles
         // (the small boxes of a batch) read the FP64 rows inside the force
         // instead: on a stream of small boxes the early loads raised the tail
-        // latency.
+        // latency.  So do the FP64 L2/L3 kernels (registers; see site_force).
         AnchRow<T> A;
-        if (!BULK && W == 1) {
+        if (!BULK && W == 1 && !(L23 && sizeof(T) == 8)) {
             const int f = j - 1;
             const bool bulk_plane = bulk_plane_of(plane_bulk, f);
             // only waves with an anchored site issue the loads
@@ -1169,9 +1170,11 @@ __global__ __launch_bounds__(NT) void k_batch_dc_control(const MemberDev* __rest
 }
 
 // L4: the kernel evaluates the chiral term (a kernel of its own, so that the
-// common L2/L3 kernels do not carry its registers).
-template <typename T, bool L23, bool L4, int MODE, int W>
-__global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_per_eu(L4 ? 1 : Tile<T, L23, W>::WAVES))) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
+// common L2/L3 kernels do not carry its registers).  TWO: held to two waves
+// per SIMD (the FP64 L2/L3 kernel for lattices whose one-wave chunks would be
+// short; LatDev::two_waves).
+template <typename T, bool L23, bool L4, int MODE, int W, bool TWO = false>
+__global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_per_eu(L4 ? 1 : (TWO ? 2 : Tile<T, L23, W>::WAVES)))) void k_march(LatDev L, Bufs<T> b, const T* __restrict__ qin,
                                                     T* __restrict__ Fout, double* partials,
                                                     FireDev* st, int k) {
     const int nblocks = (int)gridDim.x;
@@ -1583,11 +1586,11 @@ static int hip_status(hipError_t e) { return e == hipSuccess ? LQ_OK : LQ_EHIP; 
 int64_t n_step_blocks(const LatDev& L) { return L.nblocks; }
 
 // Resident blocks per compute unit of the fused FIRE step kernel.
-template <typename T, bool L23, bool L4, int W>
+template <typename T, bool L23, bool L4, int W, bool TWO = false>
 static int blocks_per_cu() {
     int n = 0;
-    hipError_t e =
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<T, L23, L4, MODE_FIRE, W>, Tile<T, L23, W>::N, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_march<T, L23, L4, MODE_FIRE, W, TWO>,
+                                                                Tile<T, L23, W>::N, 0);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 template <typename T>
@@ -1596,7 +1599,8 @@ static int blocks_per_cu_t(bool l23, bool l4, int wide) {
     if (l4) return wide ? blocks_per_cu<T, true, true, 1>() : blocks_per_cu<T, true, true, 0>();
     return wide ? blocks_per_cu<T, true, false, 1>() : blocks_per_cu<T, true, false, 0>();
 }
-int step_blocks_per_cu(int prec, bool l23, bool l4, int wide) {
+int step_blocks_per_cu(int prec, bool l23, bool l4, int wide, bool two) {
+    if (two && prec == LQ_F64 && l23 && !l4 && wide) return blocks_per_cu<double, true, false, 1, true>();
     return prec == LQ_F64 ? blocks_per_cu_t<double>(l23, l4, wide) : blocks_per_cu_t<float>(l23, l4, wide);
 }
 
@@ -1614,6 +1618,13 @@ template <typename T, int MODE, int W>
 static void launch_march(const LatDev& L, bool l23, const Bufs<T>& b, const void* q, void* F, double* partials,
                          FireDev* st, int k, hipStream_t s) {
     const dim3 g((unsigned)n_step_blocks(L));
+    if constexpr (sizeof(T) == 8 && W == 1) {
+        if (l23 && L.L4 == 0.0 && L.two_waves) {
+            k_march<T, true, false, MODE, W, true><<<g, Tile<T, true, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F,
+                                                                                 partials, st, k);
+            return;
+        }
+    }
     if (l23 && L.L4 != 0.0)
         k_march<T, true, true, MODE, W><<<g, Tile<T, true, W>::N, 0, s>>>(L, b, (const T*)q, (T*)F, partials, st, k);
     else if (l23)

@@ -152,6 +152,7 @@ struct LatDev {
     int nchunks;  // chunks of one step launch
     int nblocks;  // blocks of one step launch
     int wide;     // tile width kind of the step kernels (1 wide, 0 narrow)
+    int two_waves;  // FP64 L2/L3 wide: the step kernels held to two waves per SIMD
 };
 
 // FIRE state kept in device memory.
@@ -230,7 +231,7 @@ int launch_batch_steps(int prec, bool l23, const MemberDev* mem, int n_narrow, c
                        int tiles_narrow, int n_wide, const int* tile_off_wide, int tiles_wide,
                        const int* fin_off, int total_fin, FireDev* gather, int64_t n_steps, void* stream);
 int64_t n_step_blocks(const LatDev& L);
-int step_blocks_per_cu(int prec, bool l23, bool l4, int wide);
+int step_blocks_per_cu(int prec, bool l23, bool l4, int wide, bool two);
 int64_t n_energy_blocks(const LatDev& L);
 
 }  // namespace lq
