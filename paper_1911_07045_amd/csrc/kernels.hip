@@ -657,7 +657,8 @@ __device__ void fire_control(FireDev* st, double P, double nF2, double nv2, doub
 }
 
 // Writes this block's partials, and in the last block to arrive reduces all
-// of them in block order and runs the controller.
+// of them in block order and runs the controller (the reduction of the FIRE
+// initialisation; the step kernels run theirs at the next kernel's start).
 __device__ void grid_finish(double r[4], double* partials, FireDev* st, int nblocks, int bid,
                             double (*scratch)[4], int* flag) {
     block_reduce4(r, scratch);
@@ -1057,11 +1058,10 @@ __device__ bool dc_begin(FireDev* st, const double* partials, int nblocks, int k
 
 // One block of the force / FIRE step: tile `bid` of lattice L.  `nblocks`
 // is the lattice's own tile count; partials are indexed by tile, so the
-// reduction order does not depend on how blocks are dispatched.  DC (the
-// step kernels): the controller runs at the start of the next step kernel
-// (dc_begin) and the partials of step k go to slot k & 1; else (the FIRE
-// initialisation's reduction) the last block runs it (grid_finish).
-template <typename T, bool L23, bool L4, int MODE, int W, bool DC>
+// reduction order does not depend on how blocks are dispatched.  The
+// controller of step k - 1 runs at the start (dc_begin); the partials of
+// step k go to slot k & 1.
+template <typename T, bool L23, bool L4, int MODE, int W>
 __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, const T* __restrict__ qin,
                                            T* __restrict__ Fout, double* partials, FireDev* st,
                                            int nblocks, int bid, int k) {
@@ -1071,7 +1071,6 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
     __shared__ T sq[NS][5][PY][PX];
     __shared__ uint8_t sm[NS][PY][PX];
     __shared__ double scratch[G::N / 64][4];
-    __shared__ int last_flag;
     __shared__ double ctl_d[4];
     __shared__ int ctl_i[3];
 
@@ -1080,15 +1079,9 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
     T *q_out = nullptr, *v_out = nullptr, *F_out;
     T cv = T(1), cF = T(0), dt = T(0), hdt = T(0);
     if (STEP) {
-        int cur;
-        double dtd, c_v, c_F, mu;
-        if (DC) {
-            if (dc_begin(st, partials, nblocks, k, bid, scratch, ctl_d, ctl_i)) return;
-            cur = ctl_i[0]; dtd = ctl_d[0]; c_v = ctl_d[1]; c_F = ctl_d[2]; mu = ctl_d[3];
-        } else {
-            if (st->done) return;
-            cur = st->cur; dtd = st->dt; c_v = st->c_v; c_F = st->c_F; mu = st->mu;
-        }
+        if (dc_begin(st, partials, nblocks, k, bid, scratch, ctl_d, ctl_i)) return;
+        const int cur = ctl_i[0];
+        const double dtd = ctl_d[0], c_v = ctl_d[1], c_F = ctl_d[2], mu = ctl_d[3];
         // selects rather than indexing by cur, which would put b in scratch
         q_in = cur ? b.q[1] : b.q[0]; v_in = cur ? b.v[1] : b.v[0]; F_in = cur ? b.F[1] : b.F[0];
         q_out = cur ? b.q[0] : b.q[1]; v_out = cur ? b.v[0] : b.v[1]; F_out = cur ? b.F[0] : b.F[1];
@@ -1120,14 +1113,12 @@ __device__ __forceinline__ void step_block(const LatDev& L, const Bufs<T>& b, co
                                               zc, sq, sm, red, L.tile_planes[i]);
         }
     }
-    if (STEP && DC) {
+    if (STEP) {
         block_reduce4(red, scratch);
         if (threadIdx.x == 0) {
             double* p = partials + 4 * ((int64_t)(k & 1) * nblocks + bid);
             p[0] = red[0]; p[1] = red[1]; p[2] = red[2]; p[3] = red[3];
         }
-    } else if (STEP) {
-        grid_finish(red, partials, st, nblocks, bid, scratch, &last_flag);
     }
 }
 
@@ -1186,7 +1177,7 @@ __global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_p
         const int x = bid & 7, q = nblocks >> 3, r = nblocks & 7;
         bid = x * q + (x < r ? x : r) + (bid >> 3);
     }
-    step_block<T, L23, L4, MODE, W, true>(L, b, qin, Fout, partials, st, nblocks, bid, k);
+    step_block<T, L23, L4, MODE, W>(L, b, qin, Fout, partials, st, nblocks, bid, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -1214,8 +1205,8 @@ __global__ __launch_bounds__((Tile<T, L23, W>::N)) __attribute__((amdgpu_waves_p
         b.q[i] = (T*)M.q[i]; b.v[i] = (T*)M.v[i]; b.F[i] = (T*)M.F[i];
     }
     const LatDev& L = M.L;
-    step_block<T, L23, L23, MODE_FIRE, W, true>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
-                                                (int)blockIdx.x - off[m], k);
+    step_block<T, L23, L23, MODE_FIRE, W>(L, b, nullptr, nullptr, M.partials, M.st, M.nblocks,
+                                          (int)blockIdx.x - off[m], k);
 }
 
 __global__ void k_batch_begin(const MemberDev* __restrict__ mem, int n_members, int64_t n_steps) {
