@@ -223,10 +223,10 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
     }
     auto F = [&](int64_t c, int64_t i) { return full[(size_t)(c * P + i)] != 0; };
     // cum[c][f]: cost of planes 0 .. f - 1 of column c, a boundary plane
-    // costing g bulk planes (2.2 for the FP32 kernels, which evaluate
-    // boundary planes branch-free, measured 1.5% slower on the 128^3 colloid
-    // slab and the 512^3 patterned wall than 3)
-    const double g = 3.0;
+    // costing g bulk planes.  Measured on the 128^3 colloid slab: FP32 best
+    // with 3 (2.2 and 3.4 slower by 1.5-2%, 2.6 equal); FP64 with 2.5 (0.1444
+    // ms per step, against 0.1486 with 3, 0.1483 with 2 and 0.162 with 1.5).
+    const double g = p.prec == LQ_F64 ? 2.5 : 3.0;
     std::vector<double> cum((size_t)(ncol * (nz + 1)), 0.0);
     for (int64_t c = 0; c < ncol; ++c)
         for (int64_t f = 0; f < nz; ++f) {
