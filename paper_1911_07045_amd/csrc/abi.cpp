@@ -178,9 +178,11 @@ static bool two_waves_for(const lq_params& p, int device, bool l23, int wide) {
 // whose boundary planes cost little more, get the same equal-length cuts in
 // every column, so that neighbouring tiles march the same planes at the same
 // time and share their halo planes in L2 (measured faster than cost-balanced
-// cuts on the 256^3 multi-colloid box).  Larger lattices take 128-plane
-// chunks, which their many waves balance by themselves (chunk order: at the
-// end of plan_chunks).  Per chunk: whether every
+// cuts on the 256^3 multi-colloid box).  Larger lattices take many waves,
+// which balance by themselves: one-constant lattices in equal chunks of up
+// to 96 planes, L2/L3 lattices with the planes next to a boundary in short
+// chunks of their own and the bulk in chunks of up to CHUNK_MAX planes
+// (chunk order: at the end of plan_chunks).  Per chunk: whether every
 // site of the padded tile over the whole march is a full bulk site, and per
 // plane whether that holds for the plane and both its z-neighbours.  LQ_ZC
 // (1 .. CHUNK_MAX) forces chunks of that many planes.
@@ -239,9 +241,8 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
     for (int64_t c = 0; c < ncol; ++c)
         for (int64_t i = 0; i < P; ++i)
             nonfull[(size_t)(c * (P + 1) + i + 1)] = nonfull[(size_t)(c * (P + 1) + i)] + (F(c, i) ? 0 : 1);
-    // one wave: chunks up to CHUNK_MAX planes; many waves: up to 96 planes,
-    // cut at equal-cost points (on the 512^3 patterned wall 3.752 ms per step,
-    // against 3.785 with 128 and 3.758 with 80 on one GPU)
+    // one wave: chunks up to CHUNK_MAX planes; many waves: up to 96 planes
+    // (one-constant lattices, and the boundary runs of L2/L3 lattices, below)
     const int64_t zmin = 4;
     const bool one_wave = ncol * ((nz + CHUNK_MAX - 1) / CHUNK_MAX) <= resident;
     const int64_t zmax = one_wave ? CHUNK_MAX : 96;
@@ -320,9 +321,53 @@ static void plan_chunks(const lq_params& p, bool l23, int wide, const std::vecto
             ++blocks;
             heavy.push({worst(c, m[(size_t)c]), c});
         }
+        // Many waves with L2/L3: each run of planes whose neighbourhoods reach
+        // a boundary marches in chunks of its own (widened to WALL_Z planes,
+        // up to zmax), the bulk between the runs in chunks of up to BULK_Z
+        // planes, so that the bulk planes take no boundary chunk's per-plane
+        // mask and anchoring reads.  On the 512^3 patterned wall, ms per step:
+        // equal-cost cuts of up to 96 planes 3.757; wall chunks of 8 planes
+        // with bulk chunks of up to 128 planes 3.636, 168 3.615, 256 3.597;
+        // wall chunks of 16 or 32 planes (bulk 128) 3.656 and 3.681, of 4
+        // planes 3.624 (bulk 128) and 3.607 (bulk 168).
+        const int64_t WALL_Z = 8, BULK_Z = CHUNK_MAX;
+        auto wall_cuts = [&](int64_t c) {
+            const int64_t W = std::min<int64_t>(WALL_Z, nz);
+            std::vector<std::pair<int64_t, int64_t>> reg;
+            for (int64_t f = 0; f < nz;) {
+                if (F(c, f) && F(c, f + 1) && F(c, f + 2)) { ++f; continue; }
+                int64_t e = f;
+                while (e < nz && !(F(c, e) && F(c, e + 1) && F(c, e + 2))) ++e;
+                int64_t a = f;
+                if (e - a < W) {
+                    a = std::max<int64_t>(0, a - (W - (e - a)) / 2);
+                    e = std::min<int64_t>(nz, a + W);
+                    a = std::max<int64_t>(0, e - W);
+                }
+                if (!reg.empty() && a <= reg.back().second + zmin) reg.back().second = std::max(reg.back().second, e);
+                else reg.push_back({a, e});
+                f = e;
+            }
+            if (!reg.empty() && reg.front().first <= zmin) reg.front().first = 0;
+            if (!reg.empty() && nz - reg.back().second <= zmin) reg.back().second = nz;
+            std::vector<int64_t> z(1, 0);
+            auto span = [&](int64_t a, int64_t b, int64_t zm) {
+                const int64_t n = (b - a + zm - 1) / zm;
+                for (int64_t k = 1; k <= n; ++k) z.push_back(a + (b - a) * k / n);
+            };
+            int64_t at = 0;
+            for (const auto& r : reg) {
+                if (r.first > at) span(at, r.first, BULK_Z);
+                span(r.first, r.second, zmax);
+                at = r.second;
+            }
+            if (at < nz) span(at, nz, BULK_Z);
+            return z;
+        };
+        const bool by_walls = !one_wave && l23;
         double worst_chunk = 0.0;
         for (int64_t c = 0; c < ncol; ++c) {
-            const std::vector<int64_t> z = cuts(c, m[(size_t)c]);
+            const std::vector<int64_t> z = by_walls ? wall_cuts(c) : cuts(c, m[(size_t)c]);
             for (size_t k = 1; k < z.size(); ++k) {
                 list.push_back({(int64_t)k - 1, Chunk{(int32_t)((c % ntx) * TX), (int32_t)((c / ntx) * TY),
                                                       (int32_t)z[k - 1], (int32_t)(z[k] - z[k - 1])}});

@@ -8,7 +8,8 @@ resident blocks when the columns fit in one, cut one-constant lattices at
 the same planes in every column, balance the cost of L2/L3 blocks (packing
 two chunks into a block where whole chunks per column cannot), and give
 every XCD (each contiguous eighth of the launch order) its share of the
-wall chunks when the lattice takes many waves.
+wall chunks when the lattice takes many waves, the planes next to a
+boundary then marching in short chunks of their own.
 """
 import numpy as np
 import pytest
@@ -136,17 +137,35 @@ def test_plan_many_waves_share_walls_among_xcds():
                  count=(4, 4)),
             dict(kind="wall", axis=2, plane=nz - 1, law="rp", W=2.0, dir="normal")]
     cfg = dict(shape=(64, 64, nz), periodic=(True, True, True), objects=objs, L1=2.32, L2=1.16, L3=1.16)
-    resident = 4  # far fewer resident blocks than columns: many waves of chunks of up to 96 planes
-    chunks, bulk, cols, _, _, block = check_plan(cfg, "f32", resident)
+    resident = 4  # far fewer resident blocks than columns: many waves
+    chunks, bulk, cols, _, full, block = check_plan(cfg, "f32", resident)
     assert (np.bincount(block) == 1).all()
-    assert all(zc <= 96 for _, _, _, zc in chunks)
-    assert len(chunks) == 8 * 6
+    # every column: the planes next to each wall (0 .. 2 and 509 .. 511) in an
+    # 8-plane chunk of its own, the bulk between them in two chunks of 248
+    for runs in cols.values():
+        assert sorted(runs) == [(0, 8), (8, 248), (256, 248), (504, 8)]
     walls = np.array([(z0 == 0) or (z0 + zc == nz) for _, _, z0, zc in chunks])
+    assert (bulk == ~walls).all()
     per_xcd = walls.reshape(8, -1).sum(axis=1)
     assert (per_xcd == 2).all()
     # within an eighth: by rank, then column
     first = chunks[: len(chunks) // 8]
     assert list(first[:, 2]) == sorted(first[:, 2])
+
+
+def test_plan_many_waves_boundary_runs_inside_the_box():
+    # a sphere inside a 512-plane L2/L3 box: its planes march in non-bulk
+    # chunks of up to 96 planes, every plane outside the runs in bulk chunks
+    nz = 512
+    objs = [dict(kind="sphere", center=(31.5, 31.5, 200.0), radius=20.0, law="rp", W=2.0, dir="normal")]
+    cfg = dict(shape=(64, 64, nz), periodic=(True, True, True), objects=objs, L1=2.32, L2=1.16, L3=1.16)
+    chunks, bulk, cols, (tx, ty), full, block = check_plan(cfg, "f32", 4)
+    for (x0, y0, z0, zc), b in zip(chunks, bulk):
+        assert zc <= (256 if b else 96)
+        if not b:
+            # a non-bulk chunk holds a plane whose neighbourhood is not all full
+            assert any(not padded_all_full(full, cfg["periodic"], x0, y0, f, 1, tx, ty) for f in range(z0, z0 + zc))
+    assert bulk.any() and not bulk.all()
 
 
 @pytest.mark.parametrize("shape,periodic,prec", [((24, 24, 24), (True, True, True), "f32"),
