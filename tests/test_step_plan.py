@@ -180,6 +180,22 @@ def test_plan_small_and_ragged_boxes(shape, periodic, prec):
     check_plan(cfg, prec, 512)
 
 
+@pytest.mark.parametrize("shape,periodic", [((37, 11, 9), (True, False, True)), ((24, 24, 24), (True, True, True)),
+                                            ((5, 7, 3), (False, False, False)), ((70, 20, 300), (True, True, False)),
+                                            ((65, 9, 600), (True, True, True))])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_plan_many_waves_small_and_ragged_boxes(shape, periodic, prec):
+    # one resident block: every lattice takes many waves, L2/L3 lattices
+    # with their boundary runs in chunks of their own
+    c = [(s - 1) / 2.0 for s in shape]
+    objs = [dict(kind="sphere", center=tuple(c), radius=min(shape) / 4.0, law="rp", W=2.0, dir="normal")]
+    cfg = dict(shape=shape, periodic=periodic, objects=objs, L1=2.32, L2=0.7, L3=0.3)
+    chunks, bulk, _, _, _, block = check_plan(cfg, prec, 1)
+    assert (np.bincount(block) == 1).all()
+    cfg["L2"] = cfg["L3"] = 0.0
+    check_plan(cfg, prec, 1)
+
+
 def test_plan_rejects_bad_arguments():
     with pytest.raises(lqfire.LQError):
         lqfire.step_plan((16, 16, 16), resident=0)
